@@ -1,0 +1,412 @@
+"""Pins of the oracle's |M|^2 and reweighting against closed forms, symmetries
+and brute force.  None of these checks re-types the oracle's own formulas:
+
+* e+e- -> mu+mu-: the helicity closed form and the PDG dsigma/dOmega form.
+* g g -> t tbar at kappa = 1: the analytic spin/colour-averaged result
+  (Ellis, Stirling, Webber, "QCD and collider physics", eq. (10.12) family).
+* g g -> t tbar at kappa != 1: an explicit-colour evaluation of the three
+  Feynman diagrams with numerical Gell-Mann matrices and f^abc.
+* all multiplicities: Ward identities (kappa = 1, colour-ordered amplitudes;
+  any kappa, the abelian top-power coefficient), Lorentz invariance at
+  kappa = 1, Bose symmetry at any kappa, the polynomial structure in kappa,
+  and agreement of the FP64 build with the __float128 build.
+* eq. (3) of the paper: W' = W |M'|^2/|M|^2 and NaN where |M|^2 = 0.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import generate_events
+
+MT = 173.0
+ALS = 0.118
+EW = (1 / 132.5, 0.2312, 91.1876, 2.4952)
+PROC = {2: "gg_tt", 3: "gg_ttg", 4: "gg_ttgg", 5: "gg_ttggg"}
+
+
+def mdot(a, b):
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]
+
+
+# ------------------------------------------------------------ e+ e- -> mu+ mu-
+
+def ee_closed_form(s, c, pt):
+    alpha, sw2, mz, wz = pt
+    cw2 = 1 - sw2
+    chi = s / (s - mz ** 2 + 1j * mz * wz) / (4 * sw2 * cw2)
+    g = {"L": -0.5 + sw2, "R": sw2}
+    e4 = (4 * np.pi * alpha) ** 2
+    per = {}
+    for i in "LR":
+        for j in "LR":
+            per[i + j] = e4 * np.abs(1 + 4 * g[i] * g[j] * chi) ** 2 * ((1 + c) ** 2 if i == j else (1 - c) ** 2)
+    return per
+
+
+def ee_pdg_form(s, c, pt):
+    """64 pi^2 s dsigma/dOmega with the PDG s-channel gamma+Z cross section."""
+    alpha, sw2, mz, wz = pt
+    cw2 = 1 - sw2
+    chi = s / (s - mz ** 2 + 1j * mz * wz) / (4 * sw2 * cw2)
+    v, a = -0.5 + 2 * sw2, -0.5
+    A0 = 1 + 2 * v * v * chi.real + (v * v + a * a) ** 2 * np.abs(chi) ** 2
+    A1 = 4 * a * a * chi.real + 8 * v * v * a * a * np.abs(chi) ** 2
+    return 64 * np.pi ** 2 * s * alpha ** 2 / (4 * s) * (A0 * (1 + c * c) + A1 * c)
+
+
+def test_ee_mumu_matches_closed_forms():
+    mom = generate_events("ee_mumu", 512)
+    pts = [EW, (EW[0], EW[1], 95.0, EW[3])]
+    me = oracle.ee_mumu_me(mom, pts)
+    s = mdot(mom[0] + mom[1], mom[0] + mom[1])
+    c = (mom[0][1:] * mom[2][1:]).sum(0) / np.sqrt((mom[0][1:] ** 2).sum(0) * (mom[2][1:] ** 2).sum(0))
+    for k, pt in enumerate(pts):
+        cf = sum(ee_closed_form(s, c, pt).values()) / 4
+        assert np.max(np.abs(me[k] / cf - 1)) < 1e-12
+        assert np.max(np.abs(me[k] / ee_pdg_form(s, c, pt) - 1)) < 1e-12
+    # eq. (3) ratio for the M_Z -> 95 GeV point
+    ratio = oracle.reweight(me)[0]
+    exact = ee_pdg_form(s, c, pts[1]) / ee_pdg_form(s, c, pts[0])
+    assert np.max(np.abs(ratio / exact - 1)) < 1e-12
+
+
+def test_ee_mumu_helicity_amplitudes():
+    """Per helicity: chirality-forbidden configurations vanish exactly; the four
+    allowed ones equal e^4 |A_ij|^2 (1 +- cos theta)^2."""
+    mom = generate_events("ee_mumu", 4)
+    for e in range(4):
+        m = mom[:, :, e]
+        s = mdot(m[0] + m[1], m[0] + m[1])
+        c = m[0][1:] @ m[2][1:] / np.linalg.norm(m[0][1:]) / np.linalg.norm(m[2][1:])
+        ref = ee_closed_form(s, c, EW)
+        big = max(ref.values())
+        # (e+, e-) = (+, -) is a left-handed electron current, (-, +) right-handed
+        chir_in = {(1, -1): "L", (-1, 1): "R"}
+        chir_out = {(1, -1): "L", (-1, 1): "R"}   # (mu+, mu-)
+        for hel in itertools.product((-1, 1), repeat=4):
+            a2 = abs(oracle.ee_mumu_amp(m, hel, EW)) ** 2
+            i = chir_in.get((hel[0], hel[1]))
+            j = chir_out.get((hel[2], hel[3]))
+            if i is None or j is None:
+                assert a2 == 0.0
+            else:
+                assert abs(a2 / ref[i + j] - 1) < 1e-12
+
+
+# ------------------------------------------------------------- g g -> t tbar
+
+def esw(mom, m):
+    p1, p2, p3 = mom[0], mom[1], mom[2]
+    s = mdot(p1 + p2, p1 + p2)
+    t = mdot(p1 - p3, p1 - p3)
+    u = mdot(p2 - p3, p2 - p3)
+    t1, t2, rho = (m * m - t) / s, (m * m - u) / s, 4 * m * m / s
+    gs4 = (4 * np.pi * ALS) ** 2
+    return gs4 * (1 / (6 * t1 * t2) - 3 / 8) * (t1 ** 2 + t2 ** 2 + rho - rho ** 2 / (4 * t1 * t2))
+
+
+def test_gg_tt_matches_esw():
+    mom = generate_events("gg_tt", 256)
+    me = oracle.qcd_me(2, mom, [(ALS, MT, 1.0)])[0]
+    assert np.max(np.abs(me / esw(mom, MT) - 1)) < 1e-13
+
+
+def test_gg_tt_massless_limit_matches_esw():
+    n = 32
+    rng = np.random.default_rng(7)
+    rs = rng.uniform(100, 2000, n)
+    c = rng.uniform(-0.95, 0.95, n)
+    ph = rng.uniform(0, 2 * np.pi, n)
+    e = rs / 2
+    sn = np.sqrt(1 - c * c)
+    z = np.zeros(n)
+    mom = np.stack([np.stack([e, z, z, e]), np.stack([e, z, z, -e]),
+                    np.stack([e, e * sn * np.cos(ph), e * sn * np.sin(ph), e * c]),
+                    np.stack([e, -e * sn * np.cos(ph), -e * sn * np.sin(ph), -e * c])])
+    me = oracle.qcd_me(2, mom, [(ALS, 0.0, 1.0)])[0]
+    assert np.max(np.abs(me / esw(mom, 0.0) - 1)) < 1e-12
+
+
+def gell_mann():
+    l = np.zeros((8, 3, 3), dtype=complex)
+    l[0][0, 1] = l[0][1, 0] = 1
+    l[1][0, 1], l[1][1, 0] = -1j, 1j
+    l[2][0, 0], l[2][1, 1] = 1, -1
+    l[3][0, 2] = l[3][2, 0] = 1
+    l[4][0, 2], l[4][2, 0] = -1j, 1j
+    l[5][1, 2] = l[5][2, 1] = 1
+    l[6][1, 2], l[6][2, 1] = -1j, 1j
+    l[7] = np.diag([1, 1, -2]) / np.sqrt(3)
+    return l / 2
+
+
+T = gell_mann()
+F = np.real(-2j * (np.einsum("aij,bjk,cki->abc", T, T, T) - np.einsum("bij,ajk,cki->abc", T, T, T)))
+
+
+def test_structure_constants():
+    for a in range(8):
+        for b in range(8):
+            comm = T[a] @ T[b] - T[b] @ T[a]
+            assert np.allclose(comm, 1j * np.einsum("c,cij->ij", F[a, b], T))
+    assert abs(F[0, 1, 2] - 1) < 1e-14
+
+
+def gg_tt_explicit_colour(m, kappa, mt=MT):
+    """Spin- and colour-averaged |M|^2 of g(k1) g(k2) -> t tbar from the three
+    Feynman diagrams, colour summed with explicit Gell-Mann matrices."""
+    from test_oracle_wavefunctions import GAMMA, METRIC
+    gs = np.sqrt(4 * np.pi * ALS)
+
+    def sl(a):
+        return sum(METRIC[i, i] * GAMMA[i] * a[i] for i in range(4))
+
+    k1, k2, p3, p4 = m
+    tot = 0.0
+    for hel in itertools.product((-1, 1), repeat=4):
+        e1 = oracle.wavefunction("eps", k1, 0, hel[0])
+        e2 = oracle.wavefunction("eps", k2, 0, hel[1])
+        ub = oracle.wavefunction("ubar", p3, mt, hel[2])
+        v = oracle.wavefunction("v", p4, mt, hel[3])
+        q1, q2 = p3 - k1, p3 - k2
+        S1 = 1j * (sl(q1) + mt * np.eye(4)) / (mdot(q1, q1) - mt * mt)
+        S2 = 1j * (sl(q2) + mt * np.eye(4)) / (mdot(q2, q2) - mt * mt)
+        a1 = ub @ (1j * gs * kappa * sl(e1)) @ S1 @ (1j * gs * kappa * sl(e2)) @ v   # T^a1 T^a2
+        a2 = ub @ (1j * gs * kappa * sl(e2)) @ S2 @ (1j * gs * kappa * sl(e1)) @ v   # T^a2 T^a1
+        # s channel: three-gluon vertex g f^{c a1 a2} V_{mu nu rho}(-P, k1, k2),
+        # gluon propagator -i g_{mu sigma}/P^2, top vertex i g kappa gamma^sigma T^c
+        P = k1 + k2
+        gmat = METRIC
+        kk, pp, qq = -P, k1, k2
+        Vt = (np.einsum("mn,r->mnr", gmat, gmat @ (kk - pp)) + np.einsum("nr,m->mnr", gmat, gmat @ (pp - qq))
+              + np.einsum("rm,n->mnr", gmat, gmat @ (qq - kk)))     # all indices lower
+        Vmu = np.einsum("mnr,n,r->m", Vt, e1, e2)                    # lower index mu
+        Jup = (-1j / mdot(P, P)) * (gmat @ Vmu) * gs                  # raised, times g
+        cur = sum(METRIC[i, i] * GAMMA[i] * Jup[i] for i in range(4))
+        a3 = ub @ (1j * gs * kappa * cur) @ v                         # times f^{c a1 a2} T^c
+        # colour sum
+        M = (a1 * np.einsum("aij,bjk->abik", T, T) + a2 * np.einsum("bij,ajk->abik", T, T)
+             + a3 * np.einsum("abc,cik->abik", F, T))
+        tot += np.sum(np.abs(M) ** 2)
+    return tot / 4 / 64
+
+
+@pytest.mark.parametrize("kappa", [1.0, 0.83, 1.17])
+def test_gg_tt_explicit_colour_brute_force(kappa):
+    mom = generate_events("gg_tt", 6)
+    me = oracle.qcd_me(2, mom, [(ALS, MT, kappa)])[0]
+    for e in range(6):
+        ref = gg_tt_explicit_colour(mom[:, :, e].copy(), kappa)
+        assert abs(me[e] / ref - 1) < 1e-12
+
+
+# -------------------------------------------------------------- colour matrix
+
+def test_colour_matrix_known_values():
+    cf2 = oracle.colour_matrix(2)
+    assert [[x * 3 for x in r] for r in cf2] == [[16, -2], [-2, 16]]
+    cf3 = oracle.colour_matrix(3)
+    assert sorted(set(x * 9 for r in cf3 for x in r)) == [-8, 1, 10, 64]
+    for m in (2, 3, 4, 5):
+        cf = oracle.colour_matrix(m)
+        from fractions import Fraction
+        # diagonal: N C_F^m
+        assert all(cf[i][i] == 3 * Fraction(4, 3) ** m for i in range(len(cf)))
+        a = oracle.colour_matrix_float(m)
+        assert np.allclose(a, a.T)
+        assert np.linalg.eigvalsh(a).min() > 0
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_colour_matrix_vs_gell_mann_sum(m):
+    """CF[s][r] = sum over colours of (T^s)_{ij} conj(T^r)_{ij}, brute force."""
+    words = oracle.orderings(m)
+    acc = np.zeros((len(words), len(words)), dtype=complex)
+    for cols in itertools.product(range(8), repeat=m):
+        mats = []
+        for w in words:
+            x = np.eye(3, dtype=complex)
+            for k in w:
+                x = x @ T[cols[k]]
+            mats.append(x.reshape(-1))
+        mats = np.array(mats)
+        acc += mats @ mats.conj().T
+    assert np.allclose(acc.imag, 0, atol=1e-12)
+    assert np.allclose(acc.real, oracle.colour_matrix_float(m), atol=1e-12)
+
+
+def test_colour_matrix_vs_gell_mann_sum_sampled_n4():
+    words = oracle.orderings(4)
+    cf = oracle.colour_matrix_float(4)
+    rng = np.random.default_rng(3)
+    pairs = [(int(rng.integers(24)), int(rng.integers(24))) for _ in range(6)]
+    acc = np.zeros(len(pairs), dtype=complex)
+    for cols in itertools.product(range(8), repeat=4):
+        for k, (s, r) in enumerate(pairs):
+            a = np.eye(3, dtype=complex)
+            b = np.eye(3, dtype=complex)
+            for x in words[s]:
+                a = a @ T[cols[x]]
+            for x in words[r]:
+                b = b @ T[cols[x]]
+            acc[k] += np.sum(a * b.conj())
+    for k, (s, r) in enumerate(pairs):
+        assert abs(acc[k] - cf[s, r]) < 1e-10
+
+
+def test_colour_decomposition_explicit_sum_n3():
+    """sum over explicit colours of |sum_w T^w J_w|^2 equals J^+ CF J for the
+    oracle's own colour-ordered amplitudes (basis/ordering convention)."""
+    mom = generate_events("gg_ttg", 1)[:, :, 0]
+    J = oracle.qcd_flows(3, mom, [1, -1, 1, 1, -1], (ALS, MT, 1.1))
+    words = oracle.orderings(3)
+    tot = 0.0
+    for cols in itertools.product(range(8), repeat=3):
+        M = np.zeros((3, 3), dtype=complex)
+        for w, Jw in zip(words, J):
+            x = np.eye(3, dtype=complex)
+            for k in w:
+                x = x @ T[cols[k]]
+            M += Jw * x
+        tot += np.sum(np.abs(M) ** 2)
+    cf = oracle.colour_matrix_float(3)
+    assert abs(tot / np.real(J.conj() @ cf @ J) - 1) < 1e-12
+
+
+# ------------------------------------------------- invariances and symmetries
+
+HELS = {2: [1, -1, 1, -1], 3: [1, 1, -1, 1, -1], 4: [-1, 1, 1, -1, 1, -1], 5: [1, -1, -1, 1, 1, -1, 1]}
+
+
+@pytest.mark.parametrize("ng", [2, 3, 4, 5])
+def test_ward_identity_kappa_one(ng):
+    """At kappa = 1 every colour-ordered amplitude vanishes when one gluon's
+    polarisation is replaced by its momentum."""
+    mom = generate_events(PROC[ng], 2)
+    for e in range(2):
+        m = mom[:, :, e]
+        J = oracle.qcd_flows(ng, m, HELS[ng], (ALS, MT, 1.0))
+        scale = np.abs(J).max()
+        for leg in range(ng):
+            Jg = oracle.qcd_flows(ng, m, HELS[ng], (ALS, MT, 1.0), gauge_leg=leg)
+            # the replaced polarisation carries the gluon energy (GeV) instead of 1
+            e_leg = m[[0, 1, 4, 5, 6][leg], 0]
+            assert np.abs(Jg).max() < 1e-10 * scale * e_leg
+        # and it is violated away from kappa = 1
+        Jk = oracle.qcd_flows(ng, m, HELS[ng], (ALS, MT, 1.2), gauge_leg=0)
+        assert np.abs(Jk).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize("ng", [2, 3, 4])
+def test_abelian_ward_identity_of_top_power_coefficient(ng):
+    """J_w(kappa) is a polynomial of degree ng without constant term; the
+    coefficient of kappa^ng collects the diagrams with every gluon attached to
+    the top line, whose sum over orderings is the QED-like amplitude and obeys
+    the abelian Ward identity for any gluon."""
+    from math import comb, factorial
+    m = generate_events(PROC[ng], 1)[:, :, 0]
+
+    def lead(gauge_leg):
+        vals = [oracle.qcd_flows(ng, m, HELS[ng], (ALS, MT, float(k)), gauge_leg) for k in range(ng + 1)]
+        d = sum((-1) ** (ng - k) * comb(ng, k) * vals[k] for k in range(ng + 1))
+        return d / factorial(ng)
+
+    a = lead(-1)
+    assert abs(a.sum()) > 1e-6 * np.abs(a).max()
+    assert np.all(oracle.qcd_flows(ng, m, HELS[ng], (ALS, MT, 0.0)) == 0)
+    for leg in range(ng):
+        g = lead(leg)
+        assert np.abs(g).max() > 1e-6 * np.abs(a).max()           # single diagrams are not invariant
+        assert abs(g.sum()) < 1e-10 * np.abs(g).max() * ng          # their sum is
+
+
+def lorentz(rng):
+    b = rng.uniform(-0.6, 0.6, 3)
+    b2 = b @ b
+    g = 1 / np.sqrt(1 - b2)
+    L = np.eye(4)
+    L[0, 0] = g
+    L[0, 1:] = L[1:, 0] = g * b
+    L[1:, 1:] += (g - 1) * np.outer(b, b) / b2
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    R = np.eye(4)
+    R[1:, 1:] = q
+    return L @ R
+
+
+@pytest.mark.parametrize("ng", [3, 4])
+def test_lorentz_invariance_kappa_one(ng):
+    mom = generate_events(PROC[ng], 4)
+    rng = np.random.default_rng(11)
+    L = lorentz(rng)
+    mom2 = np.einsum("mn,inE->imE", L, mom)
+    me = oracle.qcd_me(ng, mom, [(ALS, MT, 1.0)])[0]
+    me2 = oracle.qcd_me(ng, mom2, [(ALS, MT, 1.0)])[0]
+    assert np.max(np.abs(me2 / me - 1)) < 1e-9
+
+
+@pytest.mark.parametrize("ng", [4, 5])
+def test_bose_symmetry_any_kappa(ng):
+    mom = generate_events(PROC[ng], 3)
+    pts = [(ALS, MT, 0.85), (ALS, MT, 1.15)]
+    me = oracle.qcd_me(ng, mom, pts)
+    sw = mom.copy()
+    sw[[4, 5]] = mom[[5, 4]]                      # outgoing gluons
+    assert np.max(np.abs(oracle.qcd_me(ng, sw, pts) / me - 1)) < 1e-12
+    sw = mom.copy()
+    sw[[0, 1]] = mom[[1, 0]]                      # incoming gluons
+    assert np.max(np.abs(oracle.qcd_me(ng, sw, pts) / me - 1)) < 1e-12
+
+
+@pytest.mark.parametrize("ng", [2, 3])
+def test_kappa_polynomial_structure(ng):
+    """|M(kappa)|^2 = sum_{m=2}^{2 ng} c_m kappa^m: fit from 2ng-1 points and
+    predict others; kappa = 0 gives exactly zero."""
+    mom = generate_events(PROC[ng], 3)
+    ks = np.linspace(0.5, 1.5, 2 * ng - 1)
+    extra = np.array([0.77, 1.31, 2.0])
+    me = oracle.qcd_me(ng, mom, [(ALS, MT, k) for k in np.concatenate([ks, extra, [0.0]])])
+    assert np.all(me[-1] == 0)
+    A = np.stack([ks ** p for p in range(2, 2 * ng + 1)], axis=1)
+    B = np.stack([extra ** p for p in range(2, 2 * ng + 1)], axis=1)
+    for e in range(mom.shape[2]):
+        c = np.linalg.solve(A, me[: len(ks), e])
+        pred = B @ c
+        assert np.max(np.abs(pred / me[len(ks): len(ks) + 3, e] - 1)) < 1e-9
+
+
+def test_ratio_is_one_at_kappa_one():
+    mom = generate_events("gg_ttg", 8)
+    me = oracle.qcd_me(3, mom, [(ALS, MT, 1.0), (ALS, MT, 1.0)])
+    assert np.all(oracle.reweight(me) == 1.0)
+
+
+def test_alpha_s_scaling():
+    """All tree diagrams carry g_s^ng, so |M|^2 scales as alpha_s^ng."""
+    mom = generate_events("gg_ttg", 4)
+    me = oracle.qcd_me(3, mom, [(ALS, MT, 1.1), (0.2, MT, 1.1)])
+    assert np.max(np.abs(me[1] / me[0] / (0.2 / ALS) ** 3 - 1)) < 1e-13
+
+
+@pytest.mark.parametrize("ng", [3, 4])
+def test_fp64_agrees_with_quad(ng):
+    mom = generate_events(PROC[ng], 4)
+    pts = [(ALS, MT, 1.0), (ALS, MT, 0.9)]
+    me = oracle.qcd_me(ng, mom, pts)
+    meq = oracle.qcd_me(ng, mom, pts, quad=True)
+    assert np.max(np.abs(me / meq - 1)) < 1e-12
+
+
+def test_reweight_definition():
+    me = np.array([[1.0, 0.0, 2.0, 4.0], [2.0, 3.0, 4.0, 1.0], [0.5, 1.0, 1.0, 8.0]])
+    w = np.array([3.0, 1.0, -2.0, 0.5])
+    out = oracle.reweight(me, w)
+    assert out.shape == (2, 4)
+    assert np.isnan(out[0, 1]) and np.isnan(out[1, 1])
+    assert out[0, 0] == 6.0 and out[0, 2] == -4.0 and out[0, 3] == 0.125
+    assert out[1, 0] == 1.5 and out[1, 2] == -1.0 and out[1, 3] == 1.0
+    assert np.array_equal(oracle.reweight(me)[0, [0, 2, 3]], [2.0, 2.0, 0.25])
