@@ -1,0 +1,141 @@
+#!/usr/bin/env python3
+"""Benchmark: reweighted events/s x 16 parameter points, g g -> t tbar g g.
+
+One step = one call of mgrw_reweight over the whole batch: the base |M|^2 and
+the 16 new points are evaluated in full for every event (Sec. 3.2, steps 3-8)
+and the 16 reweighted weights written (eq. (3)).  Inputs (seeded synthetic
+events, 2^23 by default) are resident in device memory before the timed
+region.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (the packed rate)
+PEAK_FP64_TFLOPS = 78.6
+HBM_TBS = 8.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flops_per_event(proc, n_points_total, n_hel):
+    path = os.path.join(HERE, "paper_2312_07440_amd", "csrc", "gen", "flops.json")
+    f = json.load(open(path))[proc]
+    return n_points_total * n_hel * f["per_helicity_flops"], f
+
+
+def cpu_baseline(proc, ng, mom_np, kap, gpu_out, sample, points_per_event):
+    """The oracle (FP64, OpenMP) on a bounded sample of the same workload."""
+    import oracle
+    sub = np.ascontiguousarray(mom_np[:, :, :sample])
+    pts = [(0.118, 173.0, 1.0)] + [(0.118, 173.0, float(k)) for k in kap]
+    t0 = time.perf_counter()
+    me = oracle.qcd_me(ng, sub, pts)
+    w = oracle.reweight(me)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    err = np.abs(gpu_out[:, :sample] / w - 1)
+    return {"value": sample * points_per_event / dt, "unit": "events*points/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {sample} events of the same sample, base + {len(kap)} points, FP64 oracle "
+                      f"({dt:.1f} s wall)"}, float(err.max()), float(np.median(err))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--proc", default="gg_ttgg")
+    ap.add_argument("--n", type=int, default=1 << 23)
+    ap.add_argument("--prec", default="mixed")
+    ap.add_argument("--points", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the reweighting is embarrassingly parallel over events and "
+              "this build measures one GPU's share; multi-GPU runs are not part of it.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2312_07440_amd as mg
+    from synth import generate_events, kappa_points
+
+    ng = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4}[args.proc]
+    log(f"generating {args.n} {args.proc} events")
+    mom_np = generate_events(args.proc, args.n)
+    kap = kappa_points(args.points)
+    dev = torch.device("cuda:0")
+    mom = torch.from_numpy(mom_np).to(dev)
+    proc = mg.Process(args.proc, args.prec)
+    proc.set_params([{"kappa_ttg": float(k)} for k in kap])
+    out = torch.empty((args.points, args.n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for i in range(args.warmup):
+        log(f"warmup {i}")
+        proc.reweight(mom, out=out)
+        torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        proc.reweight(mom, out=out)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms = float(np.mean(kern_ms))
+    log(f"step times (ms): {['%.1f' % x for x in kern_ms]}, wall {wall:.2f}s")
+
+    n_total_points = args.points + 1
+    fpe, fcounts = flops_per_event(args.proc, n_total_points, proc.n_hel)
+    achieved = fpe * args.n / (ms * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
+    value = args.n * args.points / (ms * 1e-3)
+
+    res = {
+        "metric": "reweighted events/s x16 param pts, gg->ttbar gg: exact vs surrogate at <=1% weight err",
+        "value": value,
+        "unit": "events*points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.proc} exact reweight, {args.n} events, {args.points} kappa points "
+                               f"+ base, {args.prec} precision",
+                   "events": args.n, "points": args.points, "process": args.proc,
+                   "precision": args.prec, "path": "exact"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "flops_per_event": fpe, "per_helicity_flops": fcounts["per_helicity_flops"]},
+    }
+    if not args.no_cpu_baseline:
+        sample = min(args.cpu_sample, args.n)
+        log(f"cpu baseline: oracle on {sample} events")
+        cb, emax, emed = cpu_baseline(args.proc, ng, mom_np, kap, out[:, :sample].cpu().numpy(), sample,
+                                      args.points)
+        res["cpu_baseline"] = cb
+        res["parity_sample"] = {"events": sample, "max_rel_err": emax, "median_rel_err": emed}
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,140 @@
+/*
+ * mgrw -- leading-order event reweighting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libmgrw.so.  The library evaluates, per event, the tree-level
+ * squared matrix element |M|^2 (arXiv:2312.07440, Sec. 2.1, eq. (1): the
+ * amplitude factor of the event weight) from helicity amplitudes, and the
+ * reweighted weight
+ *
+ *     W' = W |M'|^2 / |M|^2                     (Sec. 2.2, eq. (3))
+ *
+ * for a batch of events and a set of model-parameter points, following the
+ * reweighting procedure of Sec. 3.2 (1: input parameters, 3: original
+ * amplitudes, 4: overwrite parameters, 5: new amplitudes, 6: new weight,
+ * 7: repeat for all parameter sets, 8: return weights).  Event parsing
+ * (step 2) is the caller's: events arrive as device arrays.
+ *
+ * Conventions shared by all calls:
+ *  - Momenta are DEVICE pointers to float64 in "structure of arrays" layout:
+ *    mom[(i*4 + mu)*n_events + e] is component mu = (E, px, py, pz), in GeV,
+ *    of external particle i of event e, in the partonic centre-of-mass frame
+ *    (incoming partons along +z and -z).  Particle order follows the process
+ *    name: (e+, e-, mu+, mu-) or (g, g, t, tbar, g, ...).
+ *  - Event-sized inputs and outputs are DEVICE pointers owned by the caller
+ *    (for instance PyTorch tensors); the library never frees them.  Any
+ *    n_events >= 0 is accepted (no padding); n_events == 0 launches nothing.
+ *  - `stream` is a hipStream_t (NULL: the default stream).  Evaluation calls
+ *    are asynchronous and stream-ordered; argument errors are reported before
+ *    anything is launched, device faults surface at a later synchronisation.
+ *  - Return values are mgrw_status codes; on a non-OK status the calling
+ *    thread's mgrw_last_error() describes it.  No exception crosses the ABI.
+ *  - A process handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef MGRW_H
+#define MGRW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgrw_process mgrw_process;
+
+enum {
+    MGRW_OK = 0,
+    MGRW_ERR_ARG = -1,          /* invalid argument (null, range, layout) */
+    MGRW_ERR_UNSUPPORTED = -2,  /* process/precision combination not built */
+    MGRW_ERR_DEVICE = -3,       /* HIP runtime error */
+    MGRW_ERR_ALLOC = -4,        /* host allocation failed */
+    MGRW_ERR_STATE = -5         /* call not valid in the handle's state */
+};
+typedef int mgrw_status;
+
+/* Processes (tree level, Standard Model couplings; kappa scales every
+ * top-top-gluon vertex). */
+enum {
+    MGRW_EE_MUMU = 1,    /* e+ e- -> mu+ mu- via photon and Z           */
+    MGRW_GG_TT = 2,      /* g g -> t tbar                               */
+    MGRW_GG_TTG = 3,     /* g g -> t tbar g                             */
+    MGRW_GG_TTGG = 4,    /* g g -> t tbar g g                           */
+    MGRW_GG_TTGGG = 5    /* g g -> t tbar g g g                         */
+};
+
+/* Arithmetic of the amplitude chains. */
+enum {
+    MGRW_FP64 = 0,       /* everything in double                              */
+    MGRW_MIXED = 1       /* wavefunctions, vertex chains and colour sum in float;
+                            kinematics, propagator denominators, helicity sum and
+                            the ratio of eq. (3) in double                        */
+};
+
+/* One model-parameter point (runtime-modifiable parameters, Sec. 3.2: the
+ * procedure only holds for parameters that can be changed at run time).
+ * e+e- uses alpha, sw2, mz, wz; QCD processes use alphas, mt, kappa_ttg.
+ * wt (top width) must be 0: internal top lines are off shell in these
+ * processes and gauge invariance at kappa = 1 requires it. */
+typedef struct {
+    double alpha;      /* QED coupling alpha                                  */
+    double sw2;        /* sin^2(theta_W)                                      */
+    double mz, wz;     /* Z mass and width, GeV                               */
+    double alphas;     /* strong coupling alpha_s                             */
+    double mt, wt;     /* top mass and width, GeV                             */
+    double kappa_ttg;  /* scale factor of the top-top-gluon coupling          */
+} mgrw_params;
+
+#define MGRW_MAX_POINTS 64
+
+/* Create a handle for `proc` at arithmetic `prec` with base (original)
+ * parameters `base` (host pointer, copied).  Step 1 of the procedure for the
+ * original model.  Errors: MGRW_ERR_ARG (null out/base, unknown proc or prec,
+ * non-finite or unphysical parameters), MGRW_ERR_UNSUPPORTED (e+e- in mixed
+ * precision), MGRW_ERR_ALLOC. */
+mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params *base, mgrw_process **out);
+
+/* Set the new parameter points (steps 1 and 4 of the procedure): `points` is
+ * a HOST array of n_points in [1, MGRW_MAX_POINTS], copied before return;
+ * later calls use the new set, calls already launched keep theirs.  External
+ * masses (mt) must equal the base value: events are on shell for them and
+ * the new phase space must lie inside the old one (Sec. 2.2).
+ * Errors: MGRW_ERR_ARG. */
+mgrw_status mgrw_set_params(mgrw_process *p, const mgrw_params *points, int32_t n_points);
+
+/* |M|^2 of every event at one parameter point (steps 3 or 5): point = -1 is
+ * the base point, 0 <= point < n_points a point of mgrw_set_params.
+ * me_out: device float64[n_events].  Normalisation: averaged over incoming
+ * spins and colours, summed over outgoing ones, divided by n! for n identical
+ * outgoing gluons.  Errors: MGRW_ERR_ARG (null or host pointers, n_events < 0,
+ * point out of range), MGRW_ERR_STATE (point >= 0 with no points set),
+ * MGRW_ERR_DEVICE (launch failure). */
+mgrw_status mgrw_eval_me(mgrw_process *p, const double *mom, int64_t n_events, int32_t point,
+                         double *me_out, void *stream);
+
+/* Reweight (steps 3-8): for every event e and new point k,
+ *   w_out[k*n_events + e] = W_e * (|M_k|^2 / |M_base|^2),
+ * W_e = w_in[e] (device float64[n_events]) or 1 when w_in is NULL; quiet NaN
+ * where |M_base|^2 = 0 (eq. (3) requires |M|^2 != 0).  me_base_out (device
+ * float64[n_events], may be NULL) receives |M_base|^2.  All points are
+ * evaluated in full inside one kernel, so momenta are read once.
+ * Errors: as mgrw_eval_me; MGRW_ERR_STATE when no points are set. */
+mgrw_status mgrw_reweight(mgrw_process *p, const double *mom, const double *w_in, int64_t n_events,
+                          double *w_out, double *me_base_out, void *stream);
+
+/* Static properties of the process: external particles, colour flows,
+ * helicity configurations evaluated per event and point, Feynman diagrams.
+ * Any output pointer may be NULL.  Errors: MGRW_ERR_ARG (null handle). */
+mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, int *n_hel,
+                              int *n_diagrams);
+
+/* Release the handle (NULL is ignored).  Work already launched with it is
+ * unaffected: its parameters travelled with the launch. */
+void mgrw_destroy_process(mgrw_process *p);
+
+/* Text describing the calling thread's last non-OK status ("" if none). */
+const char *mgrw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGRW_H */

@@ -1,0 +1,164 @@
+"""Python binding of libmgrw (include/mgrw.h): argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of libmgrw.so; PyTorch
+provides device memory and streams.  There is no CPU fallback: if the
+library or a GPU is missing, the calls raise.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgrw.so")
+
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_DEVICE, ERR_ALLOC, ERR_STATE = 0, -1, -2, -3, -4, -5
+EE_MUMU, GG_TT, GG_TTG, GG_TTGG, GG_TTGGG = 1, 2, 3, 4, 5
+FP64, MIXED = 0, 1
+MAX_POINTS = 64
+
+PROCESS_IDS = {"ee_mumu": EE_MUMU, "gg_tt": GG_TT, "gg_ttg": GG_TTG, "gg_ttgg": GG_TTGG,
+               "gg_ttggg": GG_TTGGG}
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+
+
+class Params(ctypes.Structure):
+    """mgrw_params: one model-parameter point."""
+    _fields_ = [("alpha", ctypes.c_double), ("sw2", ctypes.c_double), ("mz", ctypes.c_double),
+                ("wz", ctypes.c_double), ("alphas", ctypes.c_double), ("mt", ctypes.c_double),
+                ("wt", ctypes.c_double), ("kappa_ttg", ctypes.c_double)]
+
+
+DEFAULT_PARAMS = dict(alpha=1 / 132.5, sw2=0.2312, mz=91.1876, wz=2.4952, alphas=0.118, mt=173.0,
+                      wt=0.0, kappa_ttg=1.0)
+
+
+def make_params(**kw):
+    d = dict(DEFAULT_PARAMS)
+    for k in kw:
+        if k not in d:
+            raise KeyError(f"unknown parameter {k}")
+    d.update(kw)
+    return Params(**d)
+
+
+class MgrwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mgrw status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmgrw.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           "(hipcc, gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i64, i32 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.mgrw_create_process.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(vp)]
+    L.mgrw_create_process.restype = ctypes.c_int
+    L.mgrw_set_params.argtypes = [vp, ctypes.POINTER(Params), i32]
+    L.mgrw_set_params.restype = ctypes.c_int
+    L.mgrw_eval_me.argtypes = [vp, dp, i64, i32, dp, vp]
+    L.mgrw_eval_me.restype = ctypes.c_int
+    L.mgrw_reweight.argtypes = [vp, dp, dp, i64, dp, dp, vp]
+    L.mgrw_reweight.restype = ctypes.c_int
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.mgrw_process_info.argtypes = [vp, ip, ip, ip, ip]
+    L.mgrw_process_info.restype = ctypes.c_int
+    L.mgrw_destroy_process.argtypes = [vp]
+    L.mgrw_destroy_process.restype = None
+    L.mgrw_last_error.argtypes = []
+    L.mgrw_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != OK:
+        raise MgrwError(status, lib().mgrw_last_error().decode())
+    return status
+
+
+def _ptr(t, name, n=None, dtype=None, allow_none=False):
+    import torch
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Process:
+    """A process handle (mgrw_create_process ... mgrw_destroy_process)."""
+
+    def __init__(self, proc, prec="mixed", base=None):
+        self.proc = PROCESS_IDS[proc] if isinstance(proc, str) else int(proc)
+        self.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        base = base if isinstance(base, Params) else make_params(**(base or {}))
+        h = ctypes.c_void_p()
+        check(lib().mgrw_create_process(self.proc, self.prec, ctypes.byref(base), ctypes.byref(h)))
+        self._h = h
+        self.n_points = 0
+        a, b, c, d = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int())
+        check(lib().mgrw_process_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        self.n_ext, self.n_flows, self.n_hel, self.n_diagrams = a.value, b.value, c.value, d.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgrw_destroy_process(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, points):
+        """points: list of Params or dicts of overrides of the defaults."""
+        pts = [p if isinstance(p, Params) else make_params(**p) for p in points]
+        arr = (Params * max(1, len(pts)))(*pts)
+        check(lib().mgrw_set_params(self._h, arr, len(pts)))
+        self.n_points = len(pts)
+
+    def _n(self, mom):
+        if mom.dim() != 3 or mom.shape[0] != self.n_ext or mom.shape[1] != 4:
+            raise ValueError(f"mom must have shape ({self.n_ext}, 4, n)")
+        return mom.shape[2]
+
+    def eval_me(self, mom, point=-1, out=None, stream=None):
+        import torch
+        n = self._n(mom)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=mom.device)
+        check(lib().mgrw_eval_me(self._h, _ptr(mom, "mom"), n, point, _ptr(out, "out", n), _stream(stream)))
+        return out
+
+    def reweight(self, mom, w_in=None, out=None, me_base_out=None, stream=None):
+        import torch
+        n = self._n(mom)
+        if out is None:
+            out = torch.empty((self.n_points, n), dtype=torch.float64, device=mom.device)
+        check(lib().mgrw_reweight(self._h, _ptr(mom, "mom"), _ptr(w_in, "w_in", n, allow_none=True), n,
+                                  _ptr(out, "out", self.n_points * n),
+                                  _ptr(me_base_out, "me_base_out", n, allow_none=True), _stream(stream)))
+        return out

@@ -1,0 +1,120 @@
+// Host build of the per-event amplitude programs -- used by the tests only.
+//
+// Two uses, neither on the product path (the Python binding never loads this
+// library):
+//  * run the generated programs on the CPU in double precision so that the
+//    generator can be validated without a GPU;
+//  * count the floating-point operations of one helicity program exactly, by
+//    instantiating the same templates with a counting scalar type.
+#include <cstdint>
+#include <cstring>
+
+#include "mgrw_event.h"
+#include "gen/gg_tt.inc"
+#include "gen/gg_ttg.inc"
+#include "gen/gg_ttgg.inc"
+
+namespace {
+
+struct cfloat {
+    double v;
+    static thread_local long long n_add, n_mul;
+    cfloat() = default;
+    constexpr cfloat(double x) : v(x) {}
+    explicit operator double() const { return v; }
+};
+thread_local long long cfloat::n_add = 0;
+thread_local long long cfloat::n_mul = 0;
+
+inline cfloat operator+(cfloat a, cfloat b) { ++cfloat::n_add; return {a.v + b.v}; }
+inline cfloat operator-(cfloat a, cfloat b) { ++cfloat::n_add; return {a.v - b.v}; }
+inline cfloat operator*(cfloat a, cfloat b) { ++cfloat::n_mul; return {a.v * b.v}; }
+inline cfloat operator-(cfloat a) { return {-a.v}; }
+inline bool operator>(cfloat a, cfloat b) { return a.v > b.v; }
+
+template <class Proc, typename T>
+void me_events(const double* mom, int64_t n, double mt, const mgrw::qcd_point* pts, int npts, double* me) {
+    for (int64_t e = 0; e < n; ++e) {
+        double p[Proc::NEXT][4];
+        for (int i = 0; i < Proc::NEXT; ++i)
+            for (int m = 0; m < 4; ++m) p[i][m] = mom[(int64_t(i) * 4 + m) * n + e];
+        mgrw::qcd_event<Proc, T> ev;
+        ev.setup(p, mt);
+        for (int k = 0; k < npts; ++k) me[int64_t(k) * n + e] = ev.me(pts[k]);
+    }
+}
+
+// counts[0..1]: add, mul of one helicity program (external wavefunctions,
+// diagram chains and colour sum); counts[2..3]: the colour sum alone;
+// counts[4..5]: external wavefunctions alone.
+template <class Proc>
+void count_ops(long long* counts) {
+    double p[Proc::NEXT][4];
+    for (int i = 0; i < Proc::NEXT; ++i)
+        for (int m = 0; m < 4; ++m) p[i][m] = 1.0 + i + 0.25 * m;
+    typename Proc::template kin<cfloat> k;
+    Proc::kinematics(p, 173.0, k);
+    typename Proc::template basis<cfloat> b;
+    Proc::external_basis(p, 173.0, b);
+    typename Proc::template coup<cfloat> c = {cfloat(1.0), cfloat(1.0), cfloat(1.0)};
+    typename Proc::template ext<cfloat> w;
+    mgrw::cx<cfloat> J[Proc::K];
+    cfloat::n_add = cfloat::n_mul = 0;
+    Proc::external(b, 5, w);
+    counts[4] = cfloat::n_add;
+    counts[5] = cfloat::n_mul;
+    Proc::amplitude(w, k, c, J);
+    long long a0 = cfloat::n_add, m0 = cfloat::n_mul;
+    (void)Proc::colour_sum(J);
+    counts[2] = cfloat::n_add - a0;
+    counts[3] = cfloat::n_mul - m0;
+    counts[0] = cfloat::n_add;
+    counts[1] = cfloat::n_mul;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgrw_host_qcd_me(int ng, const double* mom, int64_t n, double mt, const double* pts_gs_gk, int npts,
+                     double* me) {
+    if (npts < 1 || npts > 64 || n < 0) return -1;
+    mgrw::qcd_point pts[64];
+    for (int k = 0; k < npts; ++k) {
+        double gs = pts_gs_gk[2 * k], kap = pts_gs_gk[2 * k + 1];
+        pts[k] = {gs, gs * gs, gs * kap};
+    }
+    switch (ng) {
+        case 2: me_events<mgrw::gg_tt, double>(mom, n, mt, pts, npts, me); return 0;
+        case 3: me_events<mgrw::gg_ttg, double>(mom, n, mt, pts, npts, me); return 0;
+        case 4: me_events<mgrw::gg_ttgg, double>(mom, n, mt, pts, npts, me); return 0;
+        default: return -2;
+    }
+}
+
+int mgrw_host_qcd_flops(int ng, long long* counts) {
+    switch (ng) {
+        case 2: count_ops<mgrw::gg_tt>(counts); return 0;
+        case 3: count_ops<mgrw::gg_ttg>(counts); return 0;
+        case 4: count_ops<mgrw::gg_ttgg>(counts); return 0;
+        default: return -2;
+    }
+}
+
+int mgrw_host_ee_mumu_me(const double* mom, int64_t n, const double* pts6, int npts, double* me) {
+    if (npts < 1 || npts > 64 || n < 0) return -1;
+    mgrw::ew_point pts[64];
+    for (int k = 0; k < npts; ++k)
+        pts[k] = {pts6[6 * k], pts6[6 * k + 1], pts6[6 * k + 2], pts6[6 * k + 3], pts6[6 * k + 4], pts6[6 * k + 5]};
+    for (int64_t e = 0; e < n; ++e) {
+        double p[4][4];
+        for (int i = 0; i < 4; ++i)
+            for (int m = 0; m < 4; ++m) p[i][m] = mom[(int64_t(i) * 4 + m) * n + e];
+        mgrw::ee_mumu_event ev;
+        ev.setup(p);
+        for (int k = 0; k < npts; ++k) me[int64_t(k) * n + e] = ev.me(pts[k]);
+    }
+    return 0;
+}
+
+}  // extern "C"

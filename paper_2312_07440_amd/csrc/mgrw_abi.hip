@@ -1,0 +1,257 @@
+// libmgrw: HIP kernels for gfx950 and the C ABI declared in include/mgrw.h.
+//
+// One event per lane.  Each lane reads its event's momenta once (structure of
+// arrays: consecutive lanes read consecutive doubles of each component),
+// builds the helicity-independent kinematics in double, then evaluates the
+// amplitude program at the base point and at every new parameter point and
+// writes the reweighted weights (Sec. 3.2, steps 3-8; eq. (3)).  The helicity
+// loop is wave-uniform, so lanes never diverge inside the diagram chains.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/mgrw.h"
+#include "mgrw_kernels.h"
+#include "gen/gg_tt.inc"
+#include "gen/gg_ttg.inc"
+#include "gen/gg_ttgg.inc"
+
+using namespace mgrw;
+
+// Per-process launchers, one translation unit each (mgrw_qcd_<proc>.hip).
+#define MGRW_DECLARE_LAUNCHER(name)                                                                     \
+    namespace mgrw {                                                                                    \
+    hipError_t launch_##name(int fp64, const double* mom, const double* w_in, int64_t n, const qcd_launch& a, \
+                             double* out, double* me0, hipStream_t s);                                  \
+    }
+MGRW_DECLARE_LAUNCHER(gg_tt)
+MGRW_DECLARE_LAUNCHER(gg_ttg)
+MGRW_DECLARE_LAUNCHER(gg_ttgg)
+
+namespace {
+
+__global__ void __launch_bounds__(kBlock)
+ee_mumu_kernel(const double* __restrict__ mom, const double* __restrict__ w_in, int64_t n, ew_launch a,
+               double* __restrict__ out, double* __restrict__ me0_out) {
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n) return;
+    double p[4][4];
+    load_event<4>(mom, n, e, p);
+    ee_mumu_event ev;
+    ev.setup(p);
+    const double me0 = ev.me(a.pts[0]);
+    if (a.mode == 1) {
+        out[e] = me0;
+        return;
+    }
+    if (me0_out) me0_out[e] = me0;
+    const double w = w_in ? w_in[e] : 1.0;
+    for (int k = 1; k < a.npts; ++k) out[int64_t(k - 1) * n + e] = reweighted(w, ev.me(a.pts[k]), me0);
+}
+
+
+// ------------------------------------------------------------------ host side
+
+thread_local std::string g_last_error;
+
+mgrw_status fail(mgrw_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+}  // namespace
+
+struct mgrw_process {
+    int proc;
+    int prec;
+    mgrw_params base;
+    mgrw_params points[MGRW_MAX_POINTS];
+    int n_points;
+};
+
+namespace {
+
+struct proc_info {
+    int n_ext, n_flows, n_hel, n_diagrams;
+};
+
+proc_info info_of(int proc) {
+    switch (proc) {
+        case MGRW_EE_MUMU: return {4, 1, 4, 2};
+        case MGRW_GG_TT: return {mgrw::gg_tt::NEXT, mgrw::gg_tt::K, mgrw::gg_tt::NHEL, mgrw::gg_tt::NDIAG};
+        case MGRW_GG_TTG: return {mgrw::gg_ttg::NEXT, mgrw::gg_ttg::K, mgrw::gg_ttg::NHEL, mgrw::gg_ttg::NDIAG};
+        case MGRW_GG_TTGG:
+            return {mgrw::gg_ttgg::NEXT, mgrw::gg_ttgg::K, mgrw::gg_ttgg::NHEL, mgrw::gg_ttgg::NDIAG};
+        default: return {0, 0, 0, 0};
+    }
+}
+
+mgrw_status check_params(int proc, const mgrw_params& q, const char* what) {
+    const double v[8] = {q.alpha, q.sw2, q.mz, q.wz, q.alphas, q.mt, q.wt, q.kappa_ttg};
+    for (double x : v)
+        if (!finite(x)) return fail(MGRW_ERR_ARG, std::string(what) + ": non-finite parameter");
+    if (proc == MGRW_EE_MUMU) {
+        if (!(q.alpha > 0) || !(q.sw2 > 0 && q.sw2 < 1) || !(q.mz > 0) || !(q.wz >= 0))
+            return fail(MGRW_ERR_ARG, std::string(what) + ": need alpha > 0, 0 < sw2 < 1, mz > 0, wz >= 0");
+    } else {
+        if (!(q.alphas > 0) || !(q.mt > 0))
+            return fail(MGRW_ERR_ARG, std::string(what) + ": need alphas > 0 and mt > 0");
+        if (q.wt != 0.0) return fail(MGRW_ERR_ARG, std::string(what) + ": top width must be 0");
+    }
+    return MGRW_OK;
+}
+
+mgrw::qcd_point qcd_point_of(const mgrw_params& q) {
+    const double gs = std::sqrt(4.0 * M_PI * q.alphas);
+    return {gs, gs * gs, gs * q.kappa_ttg};
+}
+
+mgrw::ew_point ew_point_of(const mgrw_params& q) {
+    const double e2 = 4.0 * M_PI * q.alpha;
+    return {e2, e2 / (q.sw2 * (1.0 - q.sw2)), -0.5 + q.sw2, q.sw2, q.mz * q.mz, q.mz * q.wz};
+}
+
+mgrw_status check_device_ptr(const void* ptr, const char* what, bool allow_null) {
+    if (!ptr) {
+        if (allow_null) return MGRW_OK;
+        return fail(MGRW_ERR_ARG, std::string(what) + " is NULL");
+    }
+    hipPointerAttribute_t attr;
+    hipError_t err = hipPointerGetAttributes(&attr, ptr);
+    if (err != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MGRW_ERR_ARG, std::string(what) + " is not a HIP allocation");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(MGRW_ERR_ARG, std::string(what) + " is not device memory");
+    return MGRW_OK;
+}
+
+mgrw_status launched(hipError_t err) {
+    if (err != hipSuccess) return fail(MGRW_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(err));
+    return MGRW_OK;
+}
+
+// Shared body of eval_me (mode 1, one point) and reweight (mode 0).
+mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t n, const mgrw_params* pts,
+                int npts, int mode, double* out, double* me0, void* stream) {
+    if (n < 0) return fail(MGRW_ERR_ARG, "n_events < 0");
+    if (n == 0) return MGRW_OK;
+    mgrw_status st;
+    if ((st = check_device_ptr(mom, "mom", false)) != MGRW_OK) return st;
+    if ((st = check_device_ptr(out, mode == 1 ? "me_out" : "w_out", false)) != MGRW_OK) return st;
+    if ((st = check_device_ptr(w_in, "w_in", true)) != MGRW_OK) return st;
+    if ((st = check_device_ptr(me0, "me_base_out", true)) != MGRW_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->proc == MGRW_EE_MUMU) {
+        ew_launch a;
+        std::memset(&a, 0, sizeof a);
+        for (int k = 0; k < npts; ++k) a.pts[k] = ew_point_of(pts[k]);
+        a.npts = npts;
+        a.mode = mode;
+        const int64_t blocks = (n + kBlock - 1) / kBlock;
+        if (blocks > 0x7fffffffLL) return fail(MGRW_ERR_ARG, "n_events too large for one launch");
+        hipLaunchKernelGGL(ee_mumu_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s, mom, w_in, n, a, out, me0);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess)
+            return fail(MGRW_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(err));
+        return MGRW_OK;
+    }
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 0x7fffffffLL) return fail(MGRW_ERR_ARG, "n_events too large for one launch");
+    qcd_launch a;
+    std::memset(&a, 0, sizeof a);
+    for (int k = 0; k < npts; ++k) a.pts[k] = qcd_point_of(pts[k]);
+    a.npts = npts;
+    a.mode = mode;
+    a.mt = p->base.mt;
+    const int fp64 = p->prec == MGRW_FP64;
+    switch (p->proc) {
+        case MGRW_GG_TT: return launched(launch_gg_tt(fp64, mom, w_in, n, a, out, me0, s));
+        case MGRW_GG_TTG: return launched(launch_gg_ttg(fp64, mom, w_in, n, a, out, me0, s));
+        case MGRW_GG_TTGG: return launched(launch_gg_ttgg(fp64, mom, w_in, n, a, out, me0, s));
+        default: return fail(MGRW_ERR_UNSUPPORTED, "process not built");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgrw_process** out) {
+    if (!out) return fail(MGRW_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!base) return fail(MGRW_ERR_ARG, "base is NULL");
+    if (proc < MGRW_EE_MUMU || proc > MGRW_GG_TTGGG) return fail(MGRW_ERR_ARG, "unknown process");
+    if (prec != MGRW_FP64 && prec != MGRW_MIXED) return fail(MGRW_ERR_ARG, "unknown precision");
+    if (info_of(proc).n_ext == 0) return fail(MGRW_ERR_UNSUPPORTED, "process not built into this library");
+    if (proc == MGRW_EE_MUMU && prec != MGRW_FP64)
+        return fail(MGRW_ERR_UNSUPPORTED, "e+e- -> mu+mu- is built in FP64 only");
+    mgrw_status st = check_params(proc, *base, "base");
+    if (st != MGRW_OK) return st;
+    mgrw_process* p = new (std::nothrow) mgrw_process;
+    if (!p) return fail(MGRW_ERR_ALLOC, "out of host memory");
+    p->proc = proc;
+    p->prec = prec;
+    p->base = *base;
+    p->n_points = 0;
+    *out = p;
+    return MGRW_OK;
+}
+
+mgrw_status mgrw_set_params(mgrw_process* p, const mgrw_params* points, int32_t n_points) {
+    if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
+    if (!points) return fail(MGRW_ERR_ARG, "points is NULL");
+    if (n_points < 1 || n_points > MGRW_MAX_POINTS) return fail(MGRW_ERR_ARG, "n_points out of [1, 64]");
+    for (int k = 0; k < n_points; ++k) {
+        mgrw_status st = check_params(p->proc, points[k], "point");
+        if (st != MGRW_OK) return st;
+        if (p->proc != MGRW_EE_MUMU && points[k].mt != p->base.mt)
+            return fail(MGRW_ERR_ARG, "external masses must equal the base point's");
+    }
+    std::memcpy(p->points, points, sizeof(mgrw_params) * size_t(n_points));
+    p->n_points = n_points;
+    return MGRW_OK;
+}
+
+mgrw_status mgrw_eval_me(mgrw_process* p, const double* mom, int64_t n_events, int32_t point, double* me_out,
+                         void* stream) {
+    if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
+    if (point < -1) return fail(MGRW_ERR_ARG, "point < -1");
+    if (point >= 0 && p->n_points == 0) return fail(MGRW_ERR_STATE, "no parameter points set");
+    if (point >= p->n_points) return fail(MGRW_ERR_ARG, "point out of range");
+    const mgrw_params& q = point < 0 ? p->base : p->points[point];
+    return run(p, mom, nullptr, n_events, &q, 1, 1, me_out, nullptr, stream);
+}
+
+mgrw_status mgrw_reweight(mgrw_process* p, const double* mom, const double* w_in, int64_t n_events,
+                          double* w_out, double* me_base_out, void* stream) {
+    if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
+    if (p->n_points == 0) return fail(MGRW_ERR_STATE, "no parameter points set");
+    mgrw_params all[kMaxLaunchPoints];
+    all[0] = p->base;
+    for (int k = 0; k < p->n_points; ++k) all[k + 1] = p->points[k];
+    return run(p, mom, w_in, n_events, all, p->n_points + 1, 0, w_out, me_base_out, stream);
+}
+
+mgrw_status mgrw_process_info(const mgrw_process* p, int* n_ext, int* n_flows, int* n_hel, int* n_diagrams) {
+    if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
+    proc_info i = info_of(p->proc);
+    if (n_ext) *n_ext = i.n_ext;
+    if (n_flows) *n_flows = i.n_flows;
+    if (n_hel) *n_hel = i.n_hel;
+    if (n_diagrams) *n_diagrams = i.n_diagrams;
+    return MGRW_OK;
+}
+
+void mgrw_destroy_process(mgrw_process* p) { delete p; }
+
+const char* mgrw_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Per-event evaluation of |M|^2 at a list of parameter points.
+//
+// The same templates run in the GPU kernels (one event per lane) and in the
+// host validation build.  Structure per event (Sec. 3.2, steps 3-7 of the
+// reweighting procedure, with the parameter loop inside the event so the
+// momenta are read once):
+//   helicity-independent kinematics and propagator denominators (double);
+//   external-wavefunction bases (double, rounded to T once);
+//   for each parameter point: for each helicity: external wavefunctions,
+//   diagram chains -> colour-flow amplitudes J (T), colour sum (T),
+//   accumulated over helicities in double; normalised.
+#pragma once
+
+#include "mgrw_lorentz.h"
+
+namespace mgrw {
+
+// Couplings of one QCD parameter point, derived on the host from alpha_s and
+// kappa: g, g^2 and g*kappa.
+struct qcd_point {
+    double gs, gs2, gk;
+};
+
+// Helicity-independent state of one event: kinematics with the double
+// precision propagator denominators, and the external-wavefunction bases.
+template <class Proc, typename T>
+struct qcd_event {
+    typename Proc::template kin<T> k;
+    typename Proc::template basis<T> b;
+
+    template <typename P>
+    MGRW_HD void setup(const P& p, double mt) {
+        Proc::kinematics(p, mt, k);
+        Proc::external_basis(p, mt, b);
+    }
+
+    // |M|^2 at one parameter point: the full amplitude program for every
+    // helicity configuration, colour-summed, accumulated in double.
+    MGRW_HD double me(const qcd_point& pt) const {
+        typename Proc::template coup<T> c = {T(pt.gs), T(pt.gs2), T(pt.gk)};
+        double acc = 0.0;
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll 1
+#endif
+        for (int h = 0; h < Proc::NHEL; ++h) {
+            typename Proc::template ext<T> w;
+            Proc::external(b, h, w);
+            cx<T> J[Proc::K];
+            Proc::amplitude(w, k, c, J);
+            acc += double(Proc::colour_sum(J));
+        }
+        return acc * Proc::NORM;
+    }
+};
+
+// ------------------------------------------------------ e+ e- -> mu+ mu-
+
+// One electroweak parameter point, derived on the host: e^2 and the Z coupling
+// squared g_Z^2 = e^2/(sw^2 cw^2), chiral couplings, and the Z pole.
+struct ew_point {
+    double e2, gz2, gl, gr, mz2, mzwz;
+};
+
+// psibar gamma^mu psi' for row spinor a and column spinor b (complex vector).
+template <typename T>
+MGRW_HD v4<T> vector_current(const sp<T>& a, const sp<T>& b) {
+    // upper-right block sigma^mu = (1, s), lower-left sigmabar^mu = (1, -s)
+    v4<T> j;
+    j.t = (a.c0 * b.c2 + a.c1 * b.c3) + (a.c2 * b.c0 + a.c3 * b.c1);
+    j.x = (a.c0 * b.c3 + a.c1 * b.c2) - (a.c2 * b.c1 + a.c3 * b.c0);
+    j.y = times_i(a.c1 * b.c2 - a.c0 * b.c3) + times_i(a.c2 * b.c1 - a.c3 * b.c0);
+    j.z = (a.c0 * b.c2 - a.c1 * b.c3) - (a.c2 * b.c0 - a.c3 * b.c1);
+    return j;
+}
+
+template <typename T>
+MGRW_HD sp<T> u_in(const fermion_basis<T>& f, int lam) {
+    cx<T> c0 = lam > 0 ? f.cp0 : f.cm0;
+    cx<T> c1 = lam > 0 ? f.cp1 : f.cm1;
+    T up = lam > 0 ? f.wm : f.wp;
+    T lo = lam > 0 ? f.wp : f.wm;
+    return {c0 * up, c1 * up, c0 * lo, c1 * lo};
+}
+
+template <typename T>
+MGRW_HD sp<T> vbar_in(const fermion_basis<T>& f, int lam) {
+    sp<T> v = v_out(f, lam);
+    return {conj(v.c2), conj(v.c3), conj(v.c0), conj(v.c1)};
+}
+
+// Spin-averaged |M|^2 of e+(p0) e-(p1) -> mu+(p2) mu-(p3), gamma + Z in the s
+// channel.  With vertices -i e Q gamma^mu and -i g_Z gamma^mu (gL PL + gR PR)
+// and propagators -i g/s, -i g/(s - MZ^2 + i MZ GZ), a configuration with
+// electron chirality i and muon chirality j has
+//   M = (jout . jin) [e^2/s + g_Z^2 g_i g_j /(s - MZ^2 + i MZ GZ)]
+// up to a phase.  For massless fermions the 12 configurations with equal
+// helicities on a fermion line vanish identically and are not evaluated.
+struct ee_mumu_event {
+    cx<double> cc[2][2];   // jout . jin per (electron, muon) chirality L/R
+    double s;
+
+    template <typename P>
+    MGRW_HD void setup(const P& p) {
+        fermion_basis<double> f0 = make_fermion_basis<double>(p[0], 0.0);
+        fermion_basis<double> f1 = make_fermion_basis<double>(p[1], 0.0);
+        fermion_basis<double> f2 = make_fermion_basis<double>(p[2], 0.0);
+        fermion_basis<double> f3 = make_fermion_basis<double>(p[3], 0.0);
+        double q0 = p[0][0] + p[1][0], q1 = p[0][1] + p[1][1], q2 = p[0][2] + p[1][2], q3 = p[0][3] + p[1][3];
+        s = ((q0 - q3) * (q0 + q3) - q1 * q1) - q2 * q2;
+        // (e+, e-) helicities (+,-) form a left-handed current, (-,+) right-handed
+        for (int i = 0; i < 2; ++i) {
+            int le = i == 0 ? -1 : 1;
+            v4<double> jin = vector_current(vbar_in(f0, -le), u_in(f1, le));
+            for (int j = 0; j < 2; ++j) {
+                int lm = j == 0 ? -1 : 1;
+                v4<double> jout = vector_current(ubar_out(f3, lm), v_out(f2, -lm));
+                cc[i][j] = dot(jout, jin);
+            }
+        }
+    }
+
+    MGRW_HD double me(const ew_point& c) const {
+        double dr = s - c.mz2, di = c.mzwz, dd = 1.0 / (dr * dr + di * di);
+        cx<double> iz = {dr * dd, -di * dd};          // 1/(s - MZ^2 + i MZ GZ)
+        double acc = 0.0;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                double gi = i == 0 ? c.gl : c.gr, gj = j == 0 ? c.gl : c.gr;
+                cx<double> f = iz * (c.gz2 * gi * gj);
+                f.re = f.re + c.e2 / s;
+                cx<double> a = cc[i][j] * f;
+                acc += a.re * a.re + a.im * a.im;
+            }
+        return 0.25 * acc;
+    }
+};
+
+}  // namespace mgrw

@@ -1,0 +1,79 @@
+// Kernel templates of libmgrw (one event per lane) and the per-process
+// launcher, shared by the per-process translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/mgrw.h"
+#include "mgrw_event.h"
+
+namespace mgrw {
+
+constexpr int kBlock = 256;
+constexpr int kMaxLaunchPoints = MGRW_MAX_POINTS + 1;   // base + new points
+
+// Parameters travel by value with each launch (kernel-argument segment), so a
+// later mgrw_set_params never races with work already queued.
+struct qcd_launch {
+    mgrw::qcd_point pts[kMaxLaunchPoints];
+    int npts;        // points in pts (base first)
+    int mode;        // 0: reweight, 1: |M|^2 of pts[0] only
+    double mt;
+};
+
+struct ew_launch {
+    mgrw::ew_point pts[kMaxLaunchPoints];
+    int npts;
+    int mode;
+};
+
+template <int NEXT>
+__device__ __forceinline__ void load_event(const double* __restrict__ mom, int64_t n, int64_t e,
+                                           double (&p)[NEXT][4]) {
+#pragma unroll
+    for (int i = 0; i < NEXT; ++i)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) p[i][m] = __builtin_nontemporal_load(mom + (int64_t(i) * 4 + m) * n + e);
+}
+
+// w_out[k-1][e] = W * (me_k / me_0), NaN where me_0 = 0 (eq. (3)).
+__device__ __forceinline__ double reweighted(double w, double me, double me0) {
+    return me0 != 0.0 ? w * (me / me0) : __builtin_nan("");
+}
+
+template <class Proc, typename T>
+__global__ void __launch_bounds__(kBlock)
+qcd_kernel(const double* __restrict__ mom, const double* __restrict__ w_in, int64_t n, qcd_launch a,
+           double* __restrict__ out, double* __restrict__ me0_out) {
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n) return;   // no barriers below: early exit is safe
+    double p[Proc::NEXT][4];
+    load_event<Proc::NEXT>(mom, n, e, p);
+    mgrw::qcd_event<Proc, T> ev;
+    ev.setup(p, a.mt);
+    const double me0 = ev.me(a.pts[0]);
+    if (a.mode == 1) {
+        out[e] = me0;
+        return;
+    }
+    if (me0_out) me0_out[e] = me0;
+    const double w = w_in ? w_in[e] : 1.0;
+    for (int k = 1; k < a.npts; ++k) out[int64_t(k - 1) * n + e] = reweighted(w, ev.me(a.pts[k]), me0);
+}
+
+// Launch the reweight (mode 0) or single-point (mode 1) kernel of Proc at the
+// requested arithmetic; returns the launch status.
+template <class Proc>
+hipError_t launch_qcd(int fp64, const double* mom, const double* w_in, int64_t n, const qcd_launch& a,
+                      double* out, double* me0, hipStream_t s) {
+    const unsigned blocks = unsigned((n + kBlock - 1) / kBlock);
+    if (fp64)
+        hipLaunchKernelGGL((qcd_kernel<Proc, double>), dim3(blocks), dim3(kBlock), 0, s, mom, w_in, n, a, out, me0);
+    else
+        hipLaunchKernelGGL((qcd_kernel<Proc, float>), dim3(blocks), dim3(kBlock), 0, s, mom, w_in, n, a, out, me0);
+    return hipGetLastError();
+}
+
+}  // namespace mgrw

@@ -1,0 +1,334 @@
+// Lorentz and Dirac building blocks of tree-level helicity amplitudes.
+//
+// Conventions: metric (+,-,-,-); chiral gamma matrices
+//   gamma^mu = [[0, sigma^mu], [sigmabar^mu, 0]],  sigma^mu = (1, s),
+//   sigmabar^mu = (1, -s), upper two spinor components left-handed.
+// A slashed vector a = gamma^mu a_mu therefore has the blocks
+//   a.sigma    = [[a0 - a3, -(a1 - i a2)], [-(a1 + i a2), a0 + a3]]  (upper right)
+//   a.sigmabar = [[a0 + a3,   a1 - i a2 ], [  a1 + i a2 , a0 - a3]]  (lower left)
+//
+// Everything is a template on the real type T (float, double, or a host-side
+// counting type) so that the same source runs on the GPU, runs on the host
+// for generator validation, and yields exact operation counts.  External gluon
+// polarisations have a vanishing time component in the frame of the supplied
+// momenta; they are carried by a distinct vector type whose time component is
+// the empty type `zero`, so that helpers specialise at compile time and no
+// arithmetic on that zero is executed or counted.
+#pragma once
+
+#include <cmath>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define MGRW_HD __host__ __device__ __forceinline__
+#else
+#define MGRW_HD inline
+#endif
+
+namespace mgrw {
+
+struct zero {};
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+// --- complex arithmetic (negation is a source modifier on the GPU: free) ---
+template <typename T> MGRW_HD cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> MGRW_HD cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> MGRW_HD cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T> MGRW_HD cx<T> operator*(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> MGRW_HD cx<T> operator*(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T> MGRW_HD cx<T> operator*(T s, cx<T> a) { return {a.re * s, a.im * s}; }
+template <typename T> MGRW_HD cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+// i * a and -i * a (no arithmetic)
+template <typename T> MGRW_HD cx<T> times_i(cx<T> a) { return {-a.im, a.re}; }
+template <typename T> MGRW_HD cx<T> times_mi(cx<T> a) { return {a.im, -a.re}; }
+
+// --- the empty zero ---
+template <typename T> MGRW_HD cx<T> operator+(cx<T> a, zero) { return a; }
+template <typename T> MGRW_HD cx<T> operator+(zero, cx<T> a) { return a; }
+template <typename T> MGRW_HD cx<T> operator-(cx<T> a, zero) { return a; }
+template <typename T> MGRW_HD cx<T> operator-(zero, cx<T> a) { return -a; }
+template <typename T> MGRW_HD zero operator*(cx<T>, zero) { return {}; }
+template <typename T> MGRW_HD zero operator*(zero, cx<T>) { return {}; }
+template <typename T> MGRW_HD zero operator*(zero, T) { return {}; }
+template <typename T> MGRW_HD zero operator*(T, zero) { return {}; }
+MGRW_HD zero operator+(zero, zero) { return {}; }
+MGRW_HD zero operator-(zero, zero) { return {}; }
+MGRW_HD zero operator-(zero) { return {}; }
+MGRW_HD zero operator*(zero, zero) { return {}; }
+
+// --- four-vectors ---
+template <typename T>
+struct r4 {                    // real four-vector (momenta), upper index
+    T t, x, y, z;
+};
+template <typename T, typename Tt = cx<T>>
+struct v4 {                    // complex four-vector, upper index; Tt = zero for external gluons
+    Tt t;
+    cx<T> x, y, z;
+};
+template <typename T> using pol4 = v4<T, zero>;
+
+template <typename T> MGRW_HD r4<T> operator+(r4<T> a, r4<T> b) { return {a.t + b.t, a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename T> MGRW_HD r4<T> operator-(r4<T> a, r4<T> b) { return {a.t - b.t, a.x - b.x, a.y - b.y, a.z - b.z}; }
+
+// Minkowski products
+template <typename T, typename A, typename B>
+MGRW_HD cx<T> dot(const v4<T, A>& a, const v4<T, B>& b) {
+    return ((a.t * b.t - a.x * b.x) - a.y * b.y) - a.z * b.z;
+}
+template <typename T, typename A>
+MGRW_HD cx<T> dot(const v4<T, A>& a, const r4<T>& p) {
+    return ((a.t * p.t - a.x * p.x) - a.y * p.y) - a.z * p.z;
+}
+
+template <typename T, typename A>
+MGRW_HD v4<T> scale(const v4<T, A>& a, cx<T> s) {
+    return {a.t * s, a.x * s, a.y * s, a.z * s};
+}
+
+// --- spinors: four complex components ---
+template <typename T>
+struct sp {
+    cx<T> c0, c1, c2, c3;
+};
+
+// ---------------------------------------------------------------- vertices
+
+// Three-gluon vertex with the propagator of the combined line (Feynman gauge):
+// off-shell current of two gluon currents J1, J2 carrying incoming momenta P1,
+// P2.  Returns  coup * [(J1.J2)(P1-P2) + (J1.(P1+2P2)) J2 - (J2.(2P1+P2)) J1],
+// where coup = g / (P1+P2)^2 (the colour factor and the constant phase are
+// applied by the caller).
+template <typename T, typename A, typename B>
+MGRW_HD v4<T> vvv(const v4<T, A>& J1, const r4<T>& P1, const v4<T, B>& J2, const r4<T>& P2, T coup) {
+    r4<T> d = P1 - P2;
+    r4<T> b = {P1.t + (P2.t + P2.t), P1.x + (P2.x + P2.x), P1.y + (P2.y + P2.y), P1.z + (P2.z + P2.z)};
+    r4<T> c = {P2.t + (P1.t + P1.t), P2.x + (P1.x + P1.x), P2.y + (P1.y + P1.y), P2.z + (P1.z + P1.z)};
+    cx<T> j12 = dot(J1, J2) * coup;
+    cx<T> j1b = dot(J1, b) * coup;
+    cx<T> j2c = dot(J2, c) * coup;
+    v4<T> r;
+    r.t = (j12 * d.t + J2.t * j1b) - J1.t * j2c;
+    r.x = (j12 * d.x + J2.x * j1b) - J1.x * j2c;
+    r.y = (j12 * d.y + J2.y * j1b) - J1.y * j2c;
+    r.z = (j12 * d.z + J2.z * j1b) - J1.z * j2c;
+    return r;
+}
+
+// Four-gluon vertex with propagator: the three colour structures
+//   A = J2 (J1.J3) - J3 (J1.J2)   (colour [1,[2,3]])
+//   B = J1 (J2.J3) - J3 (J1.J2)   (colour [2,[1,3]])
+//   C = J1 (J2.J3) - J2 (J1.J3)   (colour [3,[1,2]])
+// each times coup = g^2 / P^2.  A piece built only from external gluons keeps
+// a vanishing time component (its type is deduced).
+template <typename V1, typename V2, typename V3>
+struct vvvv_out {
+    V1 A;
+    V2 B;
+    V3 C;
+};
+
+template <typename T, typename A, typename B, typename C>
+MGRW_HD auto vvvv(const v4<T, A>& J1, const v4<T, B>& J2, const v4<T, C>& J3, T coup) {
+    cx<T> d12 = dot(J1, J2) * coup, d13 = dot(J1, J3) * coup, d23 = dot(J2, J3) * coup;
+    using TA = decltype(J2.t * d13 - J3.t * d12);
+    using TB = decltype(J1.t * d23 - J3.t * d12);
+    using TC = decltype(J1.t * d23 - J2.t * d13);
+    vvvv_out<v4<T, TA>, v4<T, TB>, v4<T, TC>> o;
+    o.A.t = J2.t * d13 - J3.t * d12;
+    o.A.x = J2.x * d13 - J3.x * d12;
+    o.A.y = J2.y * d13 - J3.y * d12;
+    o.A.z = J2.z * d13 - J3.z * d12;
+    o.B.t = J1.t * d23 - J3.t * d12;
+    o.B.x = J1.x * d23 - J3.x * d12;
+    o.B.y = J1.y * d23 - J3.y * d12;
+    o.B.z = J1.z * d23 - J3.z * d12;
+    o.C.t = J1.t * d23 - J2.t * d13;
+    o.C.x = J1.x * d23 - J2.x * d13;
+    o.C.y = J1.y * d23 - J2.y * d13;
+    o.C.z = J1.z * d23 - J2.z * d13;
+    return o;
+}
+
+// Row spinor times a slashed complex vector: (a . Jslash).
+template <typename T, typename A>
+MGRW_HD sp<T> row_slash(const sp<T>& a, const v4<T, A>& J) {
+    cx<T> jp = J.t + J.z;           // J0 + J3
+    cx<T> jm = J.t - J.z;           // J0 - J3
+    cx<T> jt = J.x + times_i(J.y);  // J1 + i J2
+    cx<T> js = J.x - times_i(J.y);  // J1 - i J2
+    sp<T> b;
+    b.c0 = a.c2 * jp + a.c3 * jt;
+    b.c1 = a.c2 * js + a.c3 * jm;
+    b.c2 = a.c0 * jm - a.c1 * jt;
+    b.c3 = a.c1 * jp - a.c0 * js;
+    return b;
+}
+
+// Slashed complex vector times a column spinor: (Jslash . v).
+template <typename T, typename A>
+MGRW_HD sp<T> slash_col(const v4<T, A>& J, const sp<T>& v) {
+    cx<T> jp = J.t + J.z, jm = J.t - J.z;
+    cx<T> jt = J.x + times_i(J.y), js = J.x - times_i(J.y);
+    sp<T> b;
+    b.c0 = jm * v.c2 - js * v.c3;
+    b.c1 = jp * v.c3 - jt * v.c2;
+    b.c2 = jp * v.c0 + js * v.c1;
+    b.c3 = jt * v.c0 + jm * v.c1;
+    return b;
+}
+
+// Row spinor times (qslash + m) for a real momentum q, times a real factor.
+template <typename T>
+MGRW_HD sp<T> row_prop(const sp<T>& b, const r4<T>& q, T m, T f) {
+    T qp = q.t + q.z, qm = q.t - q.z;
+    cx<T> qt = {q.x, q.y}, qs = {q.x, -q.y};   // q1 + i q2, q1 - i q2
+    sp<T> c;
+    c.c0 = (b.c0 * m + b.c2 * qp) + b.c3 * qt;
+    c.c1 = (b.c1 * m + b.c2 * qs) + b.c3 * qm;
+    c.c2 = (b.c2 * m + b.c0 * qm) - b.c1 * qt;
+    c.c3 = (b.c3 * m + b.c1 * qp) - b.c0 * qs;
+    return {c.c0 * f, c.c1 * f, c.c2 * f, c.c3 * f};
+}
+
+// (qslash + m) times a column spinor, times a real factor.
+template <typename T>
+MGRW_HD sp<T> prop_col(const r4<T>& q, T m, const sp<T>& v, T f) {
+    T qp = q.t + q.z, qm = q.t - q.z;
+    cx<T> qt = {q.x, q.y}, qs = {q.x, -q.y};
+    sp<T> c;
+    c.c0 = (v.c0 * m + v.c2 * qm) - v.c3 * qs;
+    c.c1 = (v.c1 * m + v.c3 * qp) - v.c2 * qt;
+    c.c2 = (v.c2 * m + v.c0 * qp) + v.c1 * qs;
+    c.c3 = (v.c3 * m + v.c0 * qt) + v.c1 * qm;
+    return {c.c0 * f, c.c1 * f, c.c2 * f, c.c3 * f};
+}
+
+template <typename T>
+MGRW_HD cx<T> row_col(const sp<T>& a, const sp<T>& b) {
+    return ((a.c0 * b.c0 + a.c1 * b.c1) + a.c2 * b.c2) + a.c3 * b.c3;
+}
+
+// Top-gluon vertex followed by the top propagator, on the row (outgoing-top)
+// side:  coup * a . Jslash . (qslash + m), coup = g kappa / (q^2 - m^2).
+template <typename T, typename A>
+MGRW_HD sp<T> ffv_row(const sp<T>& a, const v4<T, A>& J, const r4<T>& q, T m, T coup) {
+    return row_prop(row_slash(a, J), q, m, coup);
+}
+
+// Top-gluon vertex followed by the top propagator on the column (antitop)
+// side: coup * (qslash + m) . Jslash . v.
+template <typename T, typename A>
+MGRW_HD sp<T> ffv_col(const v4<T, A>& J, const sp<T>& v, const r4<T>& q, T m, T coup) {
+    return prop_col(q, m, slash_col(J, v), coup);
+}
+
+// Closing vertex: coup * a . Jslash . v, coup = g kappa.
+template <typename T, typename A>
+MGRW_HD cx<T> ffv_amp(const sp<T>& a, const v4<T, A>& J, const sp<T>& v, T coup) {
+    return row_col(row_slash(a, J), v) * coup;
+}
+
+// ------------------------------------------------ external wavefunctions
+
+// Helicity-independent pieces of a gluon's polarisation vectors in the frame
+// of the given momentum: e1 = (0, cos t cos f, cos t sin f, -sin t) and
+// e2 = (0, -sin f, cos f, 0), pre-scaled by 1/sqrt(2).
+template <typename T>
+struct gluon_basis {
+    T e1x, e1y, e1z, e2x, e2y;
+};
+
+// eps(k, lam) = (-lam e1 - i e2)/sqrt2; the conjugate for an outgoing gluon.
+template <typename T>
+MGRW_HD pol4<T> gluon_pol(const gluon_basis<T>& g, int lam, bool outgoing) {
+    T s = lam > 0 ? T(-1) : T(1);          // -lam
+    pol4<T> e;
+    // imaginary part -e2 (incoming) or +e2 (outgoing): a sign choice, no arithmetic
+    T e2x = outgoing ? g.e2x : -g.e2x;
+    T e2y = outgoing ? g.e2y : -g.e2y;
+    e.x = {s > T(0) ? g.e1x : -g.e1x, e2x};
+    e.y = {s > T(0) ? g.e1y : -g.e1y, e2y};
+    e.z = {s > T(0) ? g.e1z : -g.e1z, T(0)};
+    return e;
+}
+
+// Helicity-independent pieces of a massive spinor: the two-component
+// helicity eigenstates chi_+ and chi_- of p-hat, and w_pm = sqrt(E pm |p|).
+template <typename T>
+struct fermion_basis {
+    cx<T> cp0, cp1, cm0, cm1;   // chi_+, chi_-
+    T wp, wm;                   // sqrt(E + |p|), sqrt(E - |p|)
+};
+
+// ubar(p, lam) for an outgoing fermion: u = (w_{-lam} chi_lam, w_lam chi_lam),
+// ubar = u^dagger gamma^0 = (conj(u2), conj(u3), conj(u0), conj(u1)).
+template <typename T>
+MGRW_HD sp<T> ubar_out(const fermion_basis<T>& f, int lam) {
+    cx<T> c0 = lam > 0 ? f.cp0 : f.cm0;
+    cx<T> c1 = lam > 0 ? f.cp1 : f.cm1;
+    T up = lam > 0 ? f.wm : f.wp;       // w_{-lam}
+    T lo = lam > 0 ? f.wp : f.wm;       // w_lam
+    return {conj(c0) * lo, conj(c1) * lo, conj(c0) * up, conj(c1) * up};
+}
+
+// v(p, lam) for an outgoing antifermion: (-lam w_lam chi_{-lam}, lam w_{-lam} chi_{-lam}).
+template <typename T>
+MGRW_HD sp<T> v_out(const fermion_basis<T>& f, int lam) {
+    cx<T> c0 = lam > 0 ? f.cm0 : f.cp0;
+    cx<T> c1 = lam > 0 ? f.cm1 : f.cp1;
+    T a = lam > 0 ? -f.wp : f.wm;       // -lam w_lam
+    T b = lam > 0 ? f.wm : -f.wp;       // lam w_{-lam}
+    return {c0 * a, c1 * a, c0 * b, c1 * b};
+}
+
+// Build the polarisation basis of a massless gluon from its momentum (double
+// precision in, rounded to T once).
+template <typename T, typename P>
+MGRW_HD gluon_basis<T> make_gluon_basis(const P& k) {
+    double kt = sqrt(k[1] * k[1] + k[2] * k[2]);
+    double ka = sqrt(kt * kt + k[3] * k[3]);
+    double ct = k[3] / ka, st = kt / ka;
+    double cf = 1.0, sf = 0.0;
+    if (kt > 0.0) {
+        cf = k[1] / kt;
+        sf = k[2] / kt;
+    }
+    const double r = 0.70710678118654752440;
+    return {T(ct * cf * r), T(ct * sf * r), T(-st * r), T(-sf * r), T(cf * r)};
+}
+
+// Build the spinor basis of a fermion of mass m and momentum p.  |p| + pz is
+// formed as pT^2 / (|p| - pz) when pz < 0 to avoid cancellation; on shell
+// sqrt(E - |p|) = m / sqrt(E + |p|).
+template <typename T, typename P>
+MGRW_HD fermion_basis<T> make_fermion_basis(const P& p, double m) {
+    double pt2 = p[1] * p[1] + p[2] * p[2];
+    double pa = sqrt(pt2 + p[3] * p[3]);
+    double d = p[3] >= 0.0 ? pa + p[3] : pt2 / (pa - p[3]);
+    fermion_basis<T> f;
+    if (d <= 0.0) {   // along -z
+        f.cp0 = {T(0), T(0)};
+        f.cp1 = {T(1), T(0)};
+        f.cm0 = {T(-1), T(0)};
+        f.cm1 = {T(0), T(0)};
+    } else {
+        double nrm = 1.0 / sqrt(2.0 * pa * d);
+        f.cp0 = {T(d * nrm), T(0)};
+        f.cp1 = {T(p[1] * nrm), T(p[2] * nrm)};
+        f.cm0 = {T(-p[1] * nrm), T(p[2] * nrm)};
+        f.cm1 = {T(d * nrm), T(0)};
+    }
+    double wp = sqrt(p[0] + pa);
+    f.wp = T(wp);
+    f.wm = T(m / wp);
+    return f;
+}
+
+}  // namespace mgrw

@@ -1,0 +1,471 @@
+"""Process generator for g g -> t tbar + n g (build time).
+
+Enumerates the tree-level Feynman diagrams, expands each diagram's colour
+factor onto the colour-flow basis, shares the off-shell sub-currents between
+diagrams, and emits a straight-line per-helicity program (C++ templated on the
+real type) that fills the colour-flow amplitudes J_sigma.  This is the
+"code generator" role of the event generator the paper builds on (Sec. 3.1:
+the generator emits process-specific amplitude routines, called as external
+subroutines).
+
+Diagrams.  Gluons are labelled 0..ng-1 (particles 0, 1, 4, 5, 6).  A diagram
+is the top line (from the outgoing top to the outgoing antitop) with an
+ordered sequence of pure-gluon trees attached, one per top-gluon vertex; each
+tree is a leaf, a three-gluon vertex joining two trees, or a four-gluon vertex
+joining three.  The four-gluon vertex carries three colour structures with
+different Lorentz parts; the program evaluates them as three separate pieces of
+the same diagram.  Diagram counts for ng = 2..5: 3, 16, 123, 1240.
+
+Colour.  With f^{abc} T^c = -i [T^a, T^b] a three-gluon node contributes the
+commutator of its two subtrees, a four-gluon piece the nested commutators
+[1,[2,3]], [2,[1,3]], [3,[1,2]]; the top line multiplies the tree factors in
+attachment order.  Collecting the constant phases of the Feynman rules
+(i g kappa per top vertex, i per top propagator, -i/p^2 per gluon propagator,
+g f^{abc} per three-gluon vertex, -i g^2 per four-gluon vertex) leaves every
+diagram with the common factor i times a sign (-1)^(k-1) (-1)^(#3-gluon nodes)
+for k top vertices; the common factor i is dropped (it cancels in |M|^2).
+
+Couplings are applied inside the chain (g per three-gluon vertex, g^2 per
+four-gluon vertex, g kappa per top-gluon vertex), so evaluating the program at
+a new parameter point is a full re-evaluation of the amplitude.
+"""
+from fractions import Fraction
+from functools import lru_cache
+from itertools import permutations
+
+GLUON_PARTICLE = (0, 1, 4, 5, 6)
+
+
+def bits(mask):
+    return [i for i in range(8) if mask >> i & 1]
+
+
+def lowbit(mask):
+    return mask & -mask
+
+
+def submasks(mask):
+    s = mask
+    while s:
+        yield s
+        s = (s - 1) & mask
+
+
+class Tree:
+    """A pure-gluon tree (off-shell gluon current)."""
+
+    __slots__ = ("kind", "kids", "mask", "piece", "key")
+
+    def __init__(self, kind, kids=(), mask=0, piece=None):
+        self.kind = kind            # 'leaf', 'v3', 'v4'
+        self.kids = tuple(kids)
+        self.mask = mask
+        self.piece = piece          # for v4: 'A', 'B', 'C'
+        if kind == "leaf":
+            self.key = f"g{bits(mask)[0]}"
+        else:
+            inner = ",".join(k.key for k in self.kids)
+            self.key = f"{kind}{piece or ''}({inner})"
+
+    def n_v3(self):
+        return (self.kind == "v3") + sum(k.n_v3() for k in self.kids)
+
+    def __repr__(self):
+        return self.key
+
+
+@lru_cache(maxsize=None)
+def trees(mask, split_v4=True):
+    """All trees over the gluon set `mask` (four-gluon pieces split if asked)."""
+    if mask & (mask - 1) == 0:
+        return (Tree("leaf", (), mask),)
+    out = []
+    low = lowbit(mask)
+    for s1 in submasks(mask):
+        if not s1 & low or s1 == mask:
+            continue
+        s2 = mask ^ s1
+        for t1 in trees(s1, split_v4):
+            for t2 in trees(s2, split_v4):
+                out.append(Tree("v3", (t1, t2), mask))
+    for s1 in submasks(mask):
+        if not s1 & low or s1 == mask:
+            continue
+        rest = mask ^ s1
+        low2 = lowbit(rest)
+        for s2 in submasks(rest):
+            if not s2 & low2 or s2 == rest:
+                continue
+            s3 = rest ^ s2
+            for t1 in trees(s1, split_v4):
+                for t2 in trees(s2, split_v4):
+                    for t3 in trees(s3, split_v4):
+                        if split_v4:
+                            for piece in "ABC":
+                                out.append(Tree("v4", (t1, t2, t3), mask, piece))
+                        else:
+                            out.append(Tree("v4", (t1, t2, t3), mask))
+    return tuple(out)
+
+
+def diagrams(ng, split_v4=True):
+    """Ordered sequences of trees covering all gluons (top line attachments)."""
+    full = (1 << ng) - 1
+    out = []
+
+    def rec(covered, seq):
+        rest = full ^ covered
+        for s in submasks(rest):
+            for t in trees(s, split_v4):
+                if s == rest:
+                    out.append(seq + (t,))
+                else:
+                    rec(covered | s, seq + (t,))
+
+    rec(0, ())
+    return out
+
+
+def n_diagrams(ng):
+    return len(diagrams(ng, split_v4=False))
+
+
+# ------------------------------------------------------------------- colour
+
+def _comm(a, b):
+    out = {}
+    for wa, ca in a.items():
+        for wb, cb in b.items():
+            out[wa + wb] = out.get(wa + wb, 0) + ca * cb
+            out[wb + wa] = out.get(wb + wa, 0) - ca * cb
+    return {w: c for w, c in out.items() if c}
+
+
+def _prod(a, b):
+    out = {}
+    for wa, ca in a.items():
+        for wb, cb in b.items():
+            out[wa + wb] = out.get(wa + wb, 0) + ca * cb
+    return {w: c for w, c in out.items() if c}
+
+
+def tree_colour(t):
+    if t.kind == "leaf":
+        return {(bits(t.mask)[0],): 1}
+    c = [tree_colour(k) for k in t.kids]
+    if t.kind == "v3":
+        return _comm(c[0], c[1])
+    if t.piece == "A":
+        return _comm(c[0], _comm(c[1], c[2]))
+    if t.piece == "B":
+        return _comm(c[1], _comm(c[0], c[2]))
+    return _comm(c[2], _comm(c[0], c[1]))
+
+
+def diagram_colour(seq):
+    """Coefficients of the diagram on the colour-flow basis, phases included
+    (up to the common factor i)."""
+    col = {(): 1}
+    for t in seq:
+        col = _prod(col, tree_colour(t))
+    k = len(seq)
+    sign = (-1) ** (k - 1) * (-1) ** sum(t.n_v3() for t in seq)
+    return {w: sign * c for w, c in col.items()}
+
+
+def flows(ng):
+    return list(permutations(range(ng)))
+
+
+# ---------------------------------------------------- colour matrix (own)
+
+def colour_matrix_loops(ng, nc=3):
+    """Colour matrix by index-loop counting (independent of any trace recursion).
+
+    Each gluon propagator is T^a_{ij} T^a_{kl} = 1/2 (d_il d_kj - d_ij d_kl / N).
+    For the product (T^s)_{ij} conj((T^r)_{ij}) summed over colours, choose for
+    each gluon either the first (flow) or the second (U(1)) term; the Kronecker
+    deltas then close into a number L of index loops, each worth N, and the
+    term carries (1/2)^n (-1/N)^u for u U(1) choices."""
+    words = flows(ng)
+    n = ng
+    # fundamental index slots: amplitude chain i=x0 -> x1 -> ... -> xn=j, and the
+    # conjugate chain (reversed product) closing j back to i.
+    cf = []
+    for s in words:
+        row = []
+        for r in words:
+            total = Fraction(0)
+            for choice in range(1 << n):
+                # nodes: ('a', pos) slots of amplitude matrices, ('c', pos) of conjugate
+                parent = {}
+
+                def find(x):
+                    while parent.setdefault(x, x) != x:
+                        parent[x] = parent[parent[x]]
+                        x = parent[x]
+                    return x
+
+                def union(a, b):
+                    ra, rb = find(a), find(b)
+                    if ra != rb:
+                        parent[ra] = rb
+
+                # amplitude: (T^{s1})_{a0 a1'} (T^{s2})_{a1 a2'} ... row/col index per
+                # matrix position p: row ('ar', p), col ('ac', p); chain: ac p == ar p+1
+                for p in range(n - 1):
+                    union(("ac", p), ("ar", p + 1))
+                # conjugate of (T^r)_{ij}: conj(T^a)_{kl} = (T^a)_{lk}; the conjugate
+                # chain with positions q: conj matrix q has row ('cr', q) col ('cc', q)
+                for q in range(n - 1):
+                    union(("cc", q), ("cr", q + 1))
+                # open ends: i = ar 0 = cr 0, j = ac n-1 = cc n-1
+                union(("ar", 0), ("cr", 0))
+                union(("ac", n - 1), ("cc", n - 1))
+                u = 0
+                for g in range(n):
+                    pa = s.index(g)
+                    pc = r.index(g)
+                    # amplitude factor (T^a)_{ar pa, ac pa}; conjugate factor is
+                    # (T^a)_{cc pc, cr pc} (transposed by the conjugation)
+                    if choice >> g & 1:     # -1/N d_{row col} d_{row' col'}
+                        u += 1
+                        union(("ar", pa), ("ac", pa))
+                        union(("cc", pc), ("cr", pc))
+                    else:                   # d_{ar, cr'} d_{cc', ac}
+                        union(("ar", pa), ("cr", pc))
+                        union(("cc", pc), ("ac", pa))
+                nodes = [("ar", p) for p in range(n)] + [("ac", p) for p in range(n)] + \
+                        [("cr", p) for p in range(n)] + [("cc", p) for p in range(n)]
+                loops = len({find(x) for x in nodes})
+                total += Fraction(1, 2 ** n) * Fraction(-1, nc) ** u * Fraction(nc) ** loops
+            row.append(total)
+        cf.append(row)
+    return cf
+
+
+# -------------------------------------------------------------- emission
+
+class Emitter:
+    """Straight-line program: gluon trees emitted lazily, top line as a DFS
+    over shared attachment prefixes."""
+
+    def __init__(self, ng):
+        self.ng = ng
+        self.full = (1 << ng) - 1
+        self.lines = []
+        self.tree_var = {}
+        self.nvar = 0
+        self.P_needed = set()      # incoming momentum sums used by 3-gluon vertices
+        self.iP_needed = set()     # 1/P^2 for trees over >= 2 gluons
+        self.q_needed = set()      # top momenta after attaching a set
+        self.flows = flows(ng)
+        self.flow_index = {w: i for i, w in enumerate(self.flows)}
+        self.n_amp = 0
+        self.n_jterms = 0
+        self.counts = {"vvv": 0, "vvvv": 0, "ffv_row": 0, "ffv_amp": 0}
+
+    def var(self, prefix):
+        self.nvar += 1
+        return f"{prefix}{self.nvar}"
+
+    def tree(self, t):
+        if t.key in self.tree_var:
+            return self.tree_var[t.key]
+        if t.kind == "leaf":
+            name = f"w.e{bits(t.mask)[0]}"
+            self.tree_var[t.key] = name
+            return name
+        kids = [self.tree(k) for k in t.kids]
+        self.iP_needed.add(t.mask)
+        if t.kind == "v3":
+            for k in t.kids:
+                self.P_needed.add(k.mask)
+            name = self.var("c")
+            self.lines.append(
+                f"const v4<T> {name} = vvv({kids[0]}, k.P{t.kids[0].mask}, {kids[1]}, k.P{t.kids[1].mask}, "
+                f"c.g * k.iP{t.mask});")
+            self.counts["vvv"] += 1
+            self.tree_var[t.key] = name
+            return name
+        # four-gluon vertex: emit all three pieces together
+        base = f"v4({','.join(k.key for k in t.kids)})"
+        q = self.var("c")
+        names = {p: f"{q}.{p}" for p in "ABC"}
+        self.lines.append(
+            f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, c.g2 * k.iP{t.mask});")
+        self.counts["vvvv"] += 1
+        for p in "ABC":
+            self.tree_var[f"{base.replace('v4', 'v4' + p, 1)}"] = names[p]
+        return self.tree_var[t.key]
+
+    def accumulate(self, amp, seq):
+        col = diagram_colour(seq)
+        for w, c in sorted(col.items(), key=lambda x: self.flow_index[x[0]]):
+            assert c in (1, -1), (seq, w, c)
+            j = self.flow_index[w]
+            op = "+" if c > 0 else "-"
+            self.lines.append(f"J[{j}] = J[{j}] {op} {amp};")
+            self.n_jterms += 1
+
+    def top_line(self, row, covered, seq):
+        rest = self.full ^ covered
+        # closures first: one tree over everything that is left
+        for t in trees(rest):
+            cur = self.tree(t)
+            a = self.var("a")
+            self.lines.append(f"const cx<T> {a} = ffv_amp({row}, {cur}, w.v, c.gk);")
+            self.counts["ffv_amp"] += 1
+            self.n_amp += 1
+            self.accumulate(a, seq + (t,))
+        # extensions
+        for s in sorted(submasks(rest)):
+            if s == rest:
+                continue
+            for t in trees(s):
+                cur = self.tree(t)
+                nxt = covered | s
+                self.q_needed.add(nxt)
+                name = self.var("f")
+                self.lines.append(
+                    f"const sp<T> {name} = ffv_row({row}, {cur}, k.q{nxt}, k.mt, c.gk * k.iq{nxt});")
+                self.counts["ffv_row"] += 1
+                self.top_line(name, nxt, seq + (t,))
+
+    def program(self):
+        self.top_line("w.ub", 0, ())
+        return self.lines
+
+
+def emit_process(name, ng):
+    """C++ source of the process struct for g g -> t tbar + (ng-2) g."""
+    em = Emitter(ng)
+    body = em.program()
+    K = len(em.flows)
+    next_ = ng + 2
+    cf = colour_matrix_loops(ng)
+    den = 1
+    for row in cf:
+        for x in row:
+            den = den * x.denominator // __import__("math").gcd(den, x.denominator)
+    num = [[int(x * den) for x in row] for row in cf]
+
+    P_masks = sorted(em.P_needed)
+    iP_masks = sorted(em.iP_needed)
+    q_masks = sorted(em.q_needed)
+
+    out = []
+    w = out.append
+    w(f"// Generated by paper_2312_07440_amd/gen/process.py -- g g -> t tbar + {ng - 2} g.")
+    w(f"// {n_diagrams(ng)} Feynman diagrams, {K} colour flows, {1 << next_} helicity configurations.")
+    w(f"// Per helicity: {em.counts['vvv']} three-gluon currents, {em.counts['vvvv']} four-gluon vertices,")
+    w(f"// {em.counts['ffv_row']} top-line currents, {em.counts['ffv_amp']} closing vertices, "
+      f"{em.n_jterms} colour-flow accumulations.")
+    w("#pragma once")
+    w('#include "../mgrw_lorentz.h"')
+    w("namespace mgrw {")
+    w(f"struct {name} {{")
+    w(f"  static constexpr int NG = {ng};")
+    w(f"  static constexpr int NEXT = {next_};")
+    w(f"  static constexpr int K = {K};")
+    w(f"  static constexpr int NHEL = {1 << next_};")
+    w(f"  static constexpr int NDIAG = {n_diagrams(ng)};")
+    w(f"  static constexpr int CF_DEN = {den};")
+    from math import factorial
+    w(f"  static constexpr double NORM = 1.0 / (4.0 * 64.0 * {factorial(ng - 2)}.0 * {den}.0);")
+    w("  template <typename T> struct kin {")
+    w("    T mt;")
+    for m in P_masks:
+        w(f"    r4<T> P{m};")
+    for m in iP_masks:
+        w(f"    T iP{m};")
+    for m in q_masks:
+        w(f"    r4<T> q{m};")
+        w(f"    T iq{m};")
+    w("  };")
+    w("  template <typename T> struct basis {")
+    for i in range(ng):
+        w(f"    gluon_basis<T> g{i};")
+    w("    fermion_basis<T> t, tb;")
+    w("  };")
+    w("  template <typename T> struct ext {")
+    for i in range(ng):
+        w(f"    pol4<T> e{i};")
+    w("    sp<T> ub, v;")
+    w("  };")
+    # kinematics in double
+    w("  // Helicity-independent kinematics, in double precision, rounded to T once.")
+    w("  template <typename T, typename P>")
+    w("  static MGRW_HD void kinematics(const P& p, double mt, kin<T>& k) {")
+    w("    k.mt = T(mt);")
+    w("    double kin_in[NG][4];")
+    for i, ip in enumerate(GLUON_PARTICLE[:ng]):
+        sgn = "" if ip < 2 else "-"
+        w(f"    for (int m = 0; m < 4; ++m) kin_in[{i}][m] = {sgn}p[{ip}][m];")
+    allm = sorted(set(P_masks) | set(iP_masks) | set(q_masks))
+    for m in allm:
+        terms = " + ".join(f"kin_in[{i}][m]" for i in bits(m))
+        w(f"    double S{m}[4]; for (int m = 0; m < 4; ++m) S{m}[m] = {terms};")
+    for m in P_masks:
+        w(f"    k.P{m} = {{T(S{m}[0]), T(S{m}[1]), T(S{m}[2]), T(S{m}[3])}};")
+    for m in iP_masks:
+        w(f"    k.iP{m} = T(1.0 / (((S{m}[0] * S{m}[0] - S{m}[1] * S{m}[1]) - S{m}[2] * S{m}[2]) - "
+          f"S{m}[3] * S{m}[3]));")
+    for m in q_masks:
+        w(f"    {{ double q[4]; for (int m = 0; m < 4; ++m) q[m] = p[2][m] - S{m}[m];")
+        w(f"      k.q{m} = {{T(q[0]), T(q[1]), T(q[2]), T(q[3])}};")
+        w(f"      k.iq{m} = T(1.0 / ((((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1]) - q[2] * q[2]) - mt * mt)); }}")
+    w("  }")
+    # external basis
+    w("  template <typename T, typename P>")
+    w("  static MGRW_HD void external_basis(const P& p, double mt, basis<T>& b) {")
+    for i, ip in enumerate(GLUON_PARTICLE[:ng]):
+        w(f"    b.g{i} = make_gluon_basis<T>(p[{ip}]);")
+    w("    b.t = make_fermion_basis<T>(p[2], mt);")
+    w("    b.tb = make_fermion_basis<T>(p[3], mt);")
+    w("  }")
+    # helicity selection: bit (NEXT-1-i) of h is particle i (1 = +)
+    w("  template <typename T>")
+    w("  static MGRW_HD void external(const basis<T>& b, int h, ext<T>& w) {")
+    for i, ip in enumerate(GLUON_PARTICLE[:ng]):
+        out_flag = "true" if ip >= 2 else "false"
+        w(f"    w.e{i} = gluon_pol(b.g{i}, (h >> {next_ - 1 - ip}) & 1 ? 1 : -1, {out_flag});")
+    w(f"    w.ub = ubar_out(b.t, (h >> {next_ - 1 - 2}) & 1 ? 1 : -1);")
+    w(f"    w.v = v_out(b.tb, (h >> {next_ - 1 - 3}) & 1 ? 1 : -1);")
+    w("  }")
+    w("  template <typename T> struct coup { T g, g2, gk; };")
+    w("  // Colour-flow amplitudes J (times g^0 phases dropped) of one helicity.")
+    w("  template <typename T>")
+    w("  static MGRW_HD void amplitude(const ext<T>& w, const kin<T>& k, const coup<T>& c, cx<T>* J) {")
+    w("    for (int i = 0; i < K; ++i) J[i] = {T(0), T(0)};")
+    for line in body:
+        w("    " + line)
+    w("  }")
+    # colour sum with exact integer numerators
+    w(f"  // sum_ij CF_ij Re(conj(J_i) J_j) * CF_DEN, symmetric form.")
+    w("  template <typename T>")
+    w("  static MGRW_HD T colour_sum(const cx<T>* J) {")
+    w("    T s = T(0);")
+    for i in range(K):
+        terms_re = [f"T({num[i][i]}) * J[{i}].re"]
+        terms_im = [f"T({num[i][i]}) * J[{i}].im"]
+        for j in range(i + 1, K):
+            if num[i][j]:
+                terms_re.append(f"T({2 * num[i][j]}) * J[{j}].re")
+                terms_im.append(f"T({2 * num[i][j]}) * J[{j}].im")
+        w(f"    {{ T zr = {terms_re[0]};")
+        for t in terms_re[1:]:
+            w(f"      zr = zr + {t};")
+        w(f"      T zi = {terms_im[0]};")
+        for t in terms_im[1:]:
+            w(f"      zi = zi + {t};")
+        w(f"      s = (s + zr * J[{i}].re) + zi * J[{i}].im; }}")
+    w("    return s;")
+    w("  }")
+    w("  static constexpr int CF_NUM[K][K] = {")
+    for row in num:
+        w("    {" + ", ".join(str(x) for x in row) + "},")
+    w("  };")
+    w("};")
+    w("}  // namespace mgrw")
+    return "\n".join(out) + "\n", em

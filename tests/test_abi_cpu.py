@@ -1,0 +1,74 @@
+"""The C ABI library loads and exports every symbol include/mgrw.h declares;
+argument validation that needs no device (no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2312_07440_amd import binding as bd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "mgrw.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mgrw_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("mgrw_create_process", "mgrw_set_params", "mgrw_eval_me", "mgrw_reweight",
+              "mgrw_destroy_process", "mgrw_last_error", "mgrw_process_info"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(bd.LIB_PATH):
+        pytest.skip("libmgrw.so not built")
+    lib = ctypes.CDLL(bd.LIB_PATH)
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+
+
+@pytest.fixture
+def L():
+    if not os.path.exists(bd.LIB_PATH):
+        pytest.skip("libmgrw.so not built")
+    return bd.lib()
+
+
+def test_create_validates_arguments(L):
+    h = ctypes.c_void_p()
+    base = bd.make_params()
+    assert L.mgrw_create_process(99, 0, ctypes.byref(base), ctypes.byref(h)) == bd.ERR_ARG
+    assert L.mgrw_create_process(bd.GG_TT, 7, ctypes.byref(base), ctypes.byref(h)) == bd.ERR_ARG
+    assert L.mgrw_create_process(bd.GG_TT, 0, None, ctypes.byref(h)) == bd.ERR_ARG
+    assert L.mgrw_create_process(bd.EE_MUMU, bd.MIXED, ctypes.byref(base), ctypes.byref(h)) == bd.ERR_UNSUPPORTED
+    bad = bd.make_params(wt=1.0)
+    assert L.mgrw_create_process(bd.GG_TT, 0, ctypes.byref(bad), ctypes.byref(h)) == bd.ERR_ARG
+    assert b"width" in L.mgrw_last_error()
+    nan = bd.make_params(alphas=float("nan"))
+    assert L.mgrw_create_process(bd.GG_TT, 0, ctypes.byref(nan), ctypes.byref(h)) == bd.ERR_ARG
+
+
+def test_set_params_and_state_errors(L):
+    p = bd.Process("gg_ttgg", "mixed")
+    assert (p.n_ext, p.n_flows, p.n_hel, p.n_diagrams) == (6, 24, 64, 123)
+    with pytest.raises(bd.MgrwError) as e:
+        p.set_params([{"mt": 172.0}])           # external mass change
+    assert e.value.status == bd.ERR_ARG
+    arr = (bd.Params * 1)(bd.make_params())
+    assert L.mgrw_set_params(p._h, arr, 0) == bd.ERR_ARG
+    assert L.mgrw_set_params(p._h, arr, 65) == bd.ERR_ARG
+    # no points yet: reweight and eval_me(point >= 0) are state errors (no launch)
+    assert L.mgrw_reweight(p._h, None, None, 10, None, None, None) == bd.ERR_STATE
+    assert L.mgrw_eval_me(p._h, None, 10, 0, None, None) == bd.ERR_STATE
+    p.set_params([{"kappa_ttg": 0.9}, {"kappa_ttg": 1.1}])
+    assert L.mgrw_eval_me(p._h, None, 10, 2, None, None) == bd.ERR_ARG
+    assert L.mgrw_eval_me(p._h, None, 10, -2, None, None) == bd.ERR_ARG
+    assert L.mgrw_reweight(p._h, None, None, -1, None, None, None) == bd.ERR_ARG
+    # n = 0 is accepted and launches nothing
+    assert L.mgrw_reweight(p._h, None, None, 0, None, None, None) == bd.OK
+    p.close()

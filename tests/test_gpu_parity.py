@@ -1,0 +1,222 @@
+"""GPU parity: libmgrw (through its C ABI) against the FP64 oracle.
+
+Bars: FP64 arithmetic <= 1e-12 relative per event; mixed precision <= 1e-5
+relative per event (|M|^2 and reweighted weights).  Sizes span several
+256-lane blocks with a ragged tail; the full-size case uses the benchmark's
+launch configuration and compares sampled events.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import generate_events, kappa_points
+
+pytestmark = pytest.mark.gpu
+
+ALS, MT = 0.118, 173.0
+EW = dict(alpha=1 / 132.5, sw2=0.2312, mz=91.1876, wz=2.4952)
+NG = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4}
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def qcd_case(name, n, seed_shift=0):
+    mom = generate_events(name, n, first_event=seed_shift)
+    kap = kappa_points(16)
+    w = np.random.default_rng(5).normal(size=n)
+    return mom, kap, w
+
+
+def oracle_qcd(name, mom, kap, w, base_kappa=1.0):
+    me = oracle.qcd_me(NG[name], mom, [(ALS, MT, base_kappa)] + [(ALS, MT, k) for k in kap])
+    return me, oracle.reweight(me, w)
+
+
+def relerr(a, b):
+    return np.abs(a / b - 1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,n", [("gg_tt", 1031), ("gg_ttg", 517), ("gg_ttgg", 261)])
+def test_qcd_reweight_parity(torch_dev, name, n, prec):
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    mom, kap, w = qcd_case(name, n)
+    say(f"case reweight {name} n={n} prec={prec}")
+    p = mg.Process(name, prec, {"alphas": ALS, "mt": MT})
+    p.set_params([{"alphas": ALS, "mt": MT, "kappa_ttg": float(k)} for k in kap])
+    me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    out = p.reweight(to_dev(torch, mom), w_in=to_dev(torch, w), me_base_out=me0)
+    torch.cuda.synchronize()
+    me_ref, w_ref = oracle_qcd(name, mom, kap, w)
+    e_me = relerr(me0.cpu().numpy(), me_ref[0])
+    e_w = relerr(out.cpu().numpy(), w_ref)
+    say(f"  |M|^2 rel err max {e_me.max():.3e} median {np.median(e_me):.3e}; "
+        f"W' rel err max {e_w.max():.3e} p99 {np.quantile(e_w, 0.99):.3e} median {np.median(e_w):.3e}")
+    assert e_me.max() <= TOL[prec]
+    assert e_w.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_qcd_eval_me_points(torch_dev, prec):
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    name, n = "gg_ttg", 300
+    mom, kap, _ = qcd_case(name, n)
+    say(f"case eval_me {name} n={n} prec={prec}")
+    p = mg.Process(name, prec)
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    d = to_dev(torch, mom)
+    me_b = p.eval_me(d, -1)
+    me_5 = p.eval_me(d, 5)
+    torch.cuda.synchronize()
+    ref = oracle.qcd_me(3, mom, [(ALS, MT, 1.0), (ALS, MT, float(kap[5]))])
+    assert relerr(me_b.cpu().numpy(), ref[0]).max() <= TOL[prec]
+    assert relerr(me_5.cpu().numpy(), ref[1]).max() <= TOL[prec]
+
+
+def test_ee_mumu_parity(torch_dev):
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 1031
+    mom = generate_events("ee_mumu", n)
+    say(f"case ee_mumu n={n}")
+    p = mg.Process("ee_mumu", "fp64", EW)
+    p.set_params([dict(EW, mz=95.0)])
+    me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    out = p.reweight(to_dev(torch, mom), me_base_out=me0)
+    torch.cuda.synchronize()
+    pts = [tuple(EW.values()), (EW["alpha"], EW["sw2"], 95.0, EW["wz"])]
+    ref = oracle.ee_mumu_me(mom, pts)
+    assert relerr(me0.cpu().numpy(), ref[0]).max() <= 1e-12
+    assert relerr(out.cpu().numpy()[0], oracle.reweight(ref)[0]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 257])
+def test_ragged_sizes(torch_dev, n):
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    mom, kap, w = qcd_case("gg_ttg", n, seed_shift=1000)
+    say(f"case ragged gg_ttg n={n}")
+    p = mg.Process("gg_ttg", "fp64")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap[:3]])
+    out = p.reweight(to_dev(torch, mom), w_in=to_dev(torch, w))
+    torch.cuda.synchronize()
+    me = oracle.qcd_me(3, mom, [(ALS, MT, 1.0)] + [(ALS, MT, float(k)) for k in kap[:3]])
+    assert relerr(out.cpu().numpy(), oracle.reweight(me, w)).max() <= 1e-12
+
+
+def test_zero_events_launches_nothing(torch_dev):
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    p = mg.Process("gg_tt", "mixed")
+    p.set_params([{"kappa_ttg": 1.1}])
+    mom = torch.zeros((4, 4, 0), dtype=torch.float64, device="cuda:0")
+    out = p.reweight(mom)
+    torch.cuda.synchronize()
+    assert out.shape == (1, 0)
+
+
+def test_nan_where_base_me_vanishes(torch_dev):
+    """kappa = 0 at the base point makes every diagram vanish: |M|^2 = 0 and
+    eq. (3) is undefined -> NaN."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 100
+    mom, _, w = qcd_case("gg_ttg", n)
+    say("case nan base kappa=0")
+    p = mg.Process("gg_ttg", "mixed", {"kappa_ttg": 0.0})
+    p.set_params([{"kappa_ttg": 1.0}, {"kappa_ttg": 0.0}])
+    me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    out = p.reweight(to_dev(torch, mom), w_in=to_dev(torch, w), me_base_out=me0)
+    torch.cuda.synchronize()
+    assert np.all(me0.cpu().numpy() == 0.0)
+    assert np.all(np.isnan(out.cpu().numpy()))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_same_point_gives_input_weight(torch_dev, prec):
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 200
+    mom, _, w = qcd_case("gg_ttgg", n)
+    p = mg.Process("gg_ttgg", prec)
+    p.set_params([{"kappa_ttg": 1.0}])
+    out = p.reweight(to_dev(torch, mom), w_in=to_dev(torch, w))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy()[0], w)
+
+
+def test_stream_ordering_and_determinism(torch_dev):
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 4097
+    mom, kap, w = qcd_case("gg_ttg", n)
+    p = mg.Process("gg_ttg", "mixed")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    d = to_dev(torch, mom)
+    a = p.reweight(d)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = p.reweight(d, stream=s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_host_pointer_rejected(torch_dev):
+    import paper_2312_07440_amd as mg
+    from paper_2312_07440_amd import binding as bd
+    import ctypes
+    p = mg.Process("gg_tt", "mixed")
+    p.set_params([{"kappa_ttg": 1.1}])
+    host = np.zeros((4, 4, 8))
+    out = np.zeros(8)
+    st = bd.lib().mgrw_reweight(p._h, ctypes.c_void_p(host.ctypes.data), None, 8,
+                                ctypes.c_void_p(out.ctypes.data), None, None)
+    assert st == bd.ERR_ARG
+
+
+def test_full_size_sampled_parity(torch_dev):
+    """g g -> t tbar g g at the benchmark's size (2^23 events, 16 points,
+    mixed precision), sampled events against the oracle."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 1 << 23
+    say("case full-size gg_ttgg n=2^23 mixed: generating events")
+    mom = generate_events("gg_ttgg", n)
+    kap = kappa_points(16)
+    p = mg.Process("gg_ttgg", "mixed")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    d = to_dev(torch, mom)
+    me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    say("  launching")
+    out = p.reweight(d, me_base_out=me0)
+    torch.cuda.synchronize()
+    say("  done; oracle on samples")
+    idx = np.sort(np.random.default_rng(9).choice(n, 48, replace=False))
+    idx = np.concatenate([[0, n - 1], idx])
+    sub = np.ascontiguousarray(mom[:, :, idx])
+    me_ref, w_ref = oracle_qcd("gg_ttgg", sub, kap, np.ones(len(idx)))
+    got = out[:, torch.from_numpy(idx).to("cuda:0")].cpu().numpy()
+    e = relerr(got, w_ref)
+    say(f"  sampled W' rel err max {e.max():.3e} median {np.median(e):.3e}")
+    assert relerr(me0[torch.from_numpy(idx).to("cuda:0")].cpu().numpy(), me_ref[0]).max() <= 1e-5
+    assert e.max() <= 1e-5
