@@ -21,8 +21,35 @@ struct qcd_point {
     double gs, gs2, gk;
 };
 
-// Helicity-independent state of one event: kinematics with the double
-// precision propagator denominators, and the external-wavefunction bases.
+// |M|^2 of one event at one parameter point: the full amplitude program for
+// every helicity configuration, colour-summed, accumulated in double.
+// k and b are the event's kinematics and wavefunction bases, held in
+// registers or in LDS.  On the GPU a compiler-level memory barrier at the top
+// of each helicity iteration keeps their loads inside the loop instead of
+// letting them be hoisted into registers for the whole loop.
+template <class Proc, typename T, typename KN, typename BS>
+MGRW_HD double point_me(const KN& k, const BS& b, const qcd_point& pt) {
+    typename Proc::template coup<T> c = {T(pt.gs), T(pt.gs2), T(pt.gk)};
+    double acc = 0.0;
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll 1
+#endif
+    for (int h = 0; h < Proc::NHEL; ++h) {
+#if defined(__HIP_DEVICE_COMPILE__)
+        __asm__ volatile("" ::: "memory");
+#endif
+        typename Proc::template ext<T> w;
+        Proc::template external<T>(b, h, w);
+        cx<T> J[Proc::K];
+        Proc::amplitude(w, k, c, J);
+        acc += double(Proc::colour_sum(J));
+    }
+    return acc * Proc::NORM;
+}
+
+// Helicity-independent state of one event held by value (host build, and the
+// FP64 kernels): kinematics with double-precision propagator denominators,
+// and the external-wavefunction bases.
 template <class Proc, typename T>
 struct qcd_event {
     typename Proc::template kin<T> k;
@@ -34,23 +61,7 @@ struct qcd_event {
         Proc::external_basis(p, mt, b);
     }
 
-    // |M|^2 at one parameter point: the full amplitude program for every
-    // helicity configuration, colour-summed, accumulated in double.
-    MGRW_HD double me(const qcd_point& pt) const {
-        typename Proc::template coup<T> c = {T(pt.gs), T(pt.gs2), T(pt.gk)};
-        double acc = 0.0;
-#if defined(__HIP_DEVICE_COMPILE__)
-#pragma unroll 1
-#endif
-        for (int h = 0; h < Proc::NHEL; ++h) {
-            typename Proc::template ext<T> w;
-            Proc::external(b, h, w);
-            cx<T> J[Proc::K];
-            Proc::amplitude(w, k, c, J);
-            acc += double(Proc::colour_sum(J));
-        }
-        return acc * Proc::NORM;
-    }
+    MGRW_HD double me(const qcd_point& pt) const { return point_me<Proc, T>(k, b, pt); }
 };
 
 // ------------------------------------------------------ e+ e- -> mu+ mu-
@@ -60,18 +71,6 @@ struct qcd_event {
 struct ew_point {
     double e2, gz2, gl, gr, mz2, mzwz;
 };
-
-// psibar gamma^mu psi' for row spinor a and column spinor b (complex vector).
-template <typename T>
-MGRW_HD v4<T> vector_current(const sp<T>& a, const sp<T>& b) {
-    // upper-right block sigma^mu = (1, s), lower-left sigmabar^mu = (1, -s)
-    v4<T> j;
-    j.t = (a.c0 * b.c2 + a.c1 * b.c3) + (a.c2 * b.c0 + a.c3 * b.c1);
-    j.x = (a.c0 * b.c3 + a.c1 * b.c2) - (a.c2 * b.c1 + a.c3 * b.c0);
-    j.y = times_i(a.c1 * b.c2 - a.c0 * b.c3) + times_i(a.c2 * b.c1 - a.c3 * b.c0);
-    j.z = (a.c0 * b.c2 - a.c1 * b.c3) - (a.c2 * b.c0 - a.c3 * b.c1);
-    return j;
-}
 
 template <typename T>
 MGRW_HD sp<T> u_in(const fermion_basis<T>& f, int lam) {

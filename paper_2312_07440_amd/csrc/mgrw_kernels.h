@@ -43,6 +43,40 @@ __device__ __forceinline__ double reweighted(double w, double me, double me0) {
     return me0 != 0.0 ? w * (me / me0) : __builtin_nan("");
 }
 
+// Per-lane LDS slot with an odd number of 32-bit words, so that lanes reading
+// the same member hit distinct banks.
+template <typename S>
+struct lds_slot {
+    S v;
+    float pad[(sizeof(S) / 4) % 2 == 0 ? 1 : 2];
+};
+
+// The reweight loop of one event over the points (one call site, so the
+// amplitude program is inlined once).
+template <class Proc, typename T, typename KN, typename BS>
+__device__ __forceinline__ void run_points(const KN& k, const BS& b, const qcd_launch& a, int64_t n, int64_t e,
+                                           const double* __restrict__ w_in, double* __restrict__ out,
+                                           double* __restrict__ me0_out) {
+    const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
+    double me0 = 0.0;
+#pragma unroll 1
+    for (int kp = 0; kp < a.npts; ++kp) {
+        const double me = point_me<Proc, T>(k, b, a.pts[kp]);
+        if (kp == 0) {
+            me0 = me;
+            if (a.mode == 1)
+                out[e] = me;
+            else if (me0_out)
+                me0_out[e] = me;
+        } else {
+            out[int64_t(kp - 1) * n + e] = reweighted(w, me, me0);
+        }
+    }
+}
+
+// One event per lane.  In single precision the per-lane kinematics and
+// wavefunction bases live in LDS (each lane owns a slot; no barriers); in
+// double precision they stay in registers.
 template <class Proc, typename T>
 __global__ void __launch_bounds__(kBlock)
 qcd_kernel(const double* __restrict__ mom, const double* __restrict__ w_in, int64_t n, qcd_launch a,
@@ -51,16 +85,23 @@ qcd_kernel(const double* __restrict__ mom, const double* __restrict__ w_in, int6
     if (e >= n) return;   // no barriers below: early exit is safe
     double p[Proc::NEXT][4];
     load_event<Proc::NEXT>(mom, n, e, p);
-    mgrw::qcd_event<Proc, T> ev;
-    ev.setup(p, a.mt);
-    const double me0 = ev.me(a.pts[0]);
-    if (a.mode == 1) {
-        out[e] = me0;
-        return;
+    using KinT = typename Proc::template kin<T>;
+    using BasT = typename Proc::template basis<T>;
+    if constexpr (sizeof(T) == 4) {
+        __shared__ lds_slot<KinT> ks[kBlock];
+        __shared__ lds_slot<BasT> bs[kBlock];
+        KinT& k = ks[threadIdx.x].v;
+        BasT& b = bs[threadIdx.x].v;
+        Proc::kinematics(p, a.mt, k);
+        Proc::external_basis(p, a.mt, b);
+        run_points<Proc, T>(k, b, a, n, e, w_in, out, me0_out);
+    } else {
+        KinT k;
+        BasT b;
+        Proc::kinematics(p, a.mt, k);
+        Proc::external_basis(p, a.mt, b);
+        run_points<Proc, T>(k, b, a, n, e, w_in, out, me0_out);
     }
-    if (me0_out) me0_out[e] = me0;
-    const double w = w_in ? w_in[e] : 1.0;
-    for (int k = 1; k < a.npts; ++k) out[int64_t(k - 1) * n + e] = reweighted(w, ev.me(a.pts[k]), me0);
 }
 
 // Launch the reweight (mode 0) or single-point (mode 1) kernel of Proc at the

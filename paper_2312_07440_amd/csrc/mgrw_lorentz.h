@@ -25,6 +25,15 @@
 #define MGRW_HD inline
 #endif
 
+// Scheduling fence between independent groups of a generated program: keeps
+// the device scheduler from interleaving groups (and so from growing the
+// live register set); no effect on the host.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MGRW_SCHED_BARRIER() __builtin_amdgcn_sched_barrier(0)
+#else
+#define MGRW_SCHED_BARRIER() ((void)0)
+#endif
+
 namespace mgrw {
 
 struct zero {};
@@ -233,6 +242,26 @@ MGRW_HD sp<T> ffv_col(const v4<T, A>& J, const sp<T>& v, const r4<T>& q, T m, T 
 template <typename T, typename A>
 MGRW_HD cx<T> ffv_amp(const sp<T>& a, const v4<T, A>& J, const sp<T>& v, T coup) {
     return row_col(row_slash(a, J), v) * coup;
+}
+
+// psibar gamma^mu psi' for row spinor a and column spinor b (complex vector).
+template <typename T>
+MGRW_HD v4<T> vector_current(const sp<T>& a, const sp<T>& b) {
+    // upper-right block sigma^mu = (1, s), lower-left sigmabar^mu = (1, -s)
+    v4<T> j;
+    j.t = (a.c0 * b.c2 + a.c1 * b.c3) + (a.c2 * b.c0 + a.c3 * b.c1);
+    j.x = (a.c0 * b.c3 + a.c1 * b.c2) - (a.c2 * b.c1 + a.c3 * b.c0);
+    j.y = times_i(a.c1 * b.c2 - a.c0 * b.c3) + times_i(a.c2 * b.c1 - a.c3 * b.c0);
+    j.z = (a.c0 * b.c2 - a.c1 * b.c3) - (a.c2 * b.c0 - a.c3 * b.c1);
+    return j;
+}
+
+// The t tbar current f * (ubar gamma^mu v): the off-shell gluon emitted by the
+// top line with no other attachment (f carries g kappa and 1/P^2).
+template <typename T>
+MGRW_HD v4<T> tt_current(const sp<T>& ub, const sp<T>& v, T f) {
+    v4<T> j = vector_current(ub, v);
+    return {j.t * f, j.x * f, j.y * f, j.z * f};
 }
 
 // ------------------------------------------------ external wavefunctions

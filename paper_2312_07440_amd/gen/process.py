@@ -246,35 +246,85 @@ def colour_matrix_loops(ng, nc=3):
 
 # -------------------------------------------------------------- emission
 
-class Emitter:
-    """Straight-line program: gluon trees emitted lazily, top line as a DFS
-    over shared attachment prefixes."""
+def popcount(m):
+    return bin(m).count("1")
 
-    def __init__(self, ng):
+
+def closing(seq):
+    """Where a diagram's amplitude is closed.
+
+    ('leaf', j): all blocks are single gluons; closed at top vertex j.
+    ('ttg', U, j): closed at the top-gluon vertex of block j, the first of the
+                   largest gluon trees (over the gluon set U).
+    ('root', U, None): a single tree spans every gluon; closed at that tree's
+                   root gluon vertex against the t tbar current; U is the set
+                   of the root's largest child."""
+    sizes = [popcount(t.mask) for t in seq]
+    big = max(sizes)
+    if big == 1:
+        return ("leaf", None, (len(seq) - 1) // 2)
+    j = sizes.index(big)
+    if len(seq) == 1:
+        kids = seq[0].kids
+        ks = [popcount(k.mask) for k in kids]
+        return ("root", kids[ks.index(max(ks))].mask, None)
+    return ("ttg", seq[j].mask, j)
+
+
+class Emitter:
+    """Straight-line per-helicity program, grouped by closing tree.
+
+    Every diagram is closed at one vertex (see `closing`): the amplitude is
+    the contraction at that vertex of the row current from the top
+    (L = ubar Gamma S Gamma S ...), the column current from the antitop
+    (R = ... S Gamma S Gamma v) and the gluon tree attached there, or, for a
+    tree spanning all gluons, of the tree's root children with the t tbar
+    current.  Diagrams are grouped by the gluon set of their closing tree, and
+    the sub-currents a group builds are private to it (rebuilt if another group
+    needs them), so every intermediate dies at the end of its group; the
+    external wavefunctions, the t tbar current and the single-gluon row and
+    column currents are shared by all groups."""
+
+    def __init__(self, ng, global_leaf_lr=True):
         self.ng = ng
         self.full = (1 << ng) - 1
         self.lines = []
-        self.tree_var = {}
         self.nvar = 0
-        self.P_needed = set()      # incoming momentum sums used by 3-gluon vertices
-        self.iP_needed = set()     # 1/P^2 for trees over >= 2 gluons
-        self.q_needed = set()      # top momenta after attaching a set
+        self.P_needed = set()      # incoming momentum sums entering three-gluon vertices
+        self.iP_needed = set()     # 1/P^2 of internal gluon lines
+        self.qL_needed = set()     # top-side propagators: q = p_t - P(S)
+        self.qR_needed = set()     # antitop-side propagators: q = P(S) - p_tbar
         self.flows = flows(ng)
         self.flow_index = {w: i for i, w in enumerate(self.flows)}
         self.n_amp = 0
         self.n_jterms = 0
-        self.counts = {"vvv": 0, "vvvv": 0, "ffv_row": 0, "ffv_amp": 0}
+        self.counts = {"vvv": 0, "vvvv": 0, "ffv_row": 0, "ffv_col": 0, "ffv_amp": 0, "vvv_amp": 0,
+                       "vvvv_amp": 0, "tt_current": 0}
+        self.global_cache = {}
+        self.cache = {}
+        self.global_leaf_lr = global_leaf_lr
 
     def var(self, prefix):
         self.nvar += 1
         return f"{prefix}{self.nvar}"
 
+    def emit(self, line):
+        self.lines.append(line)
+
+    def lookup(self, key):
+        if key in self.cache:
+            return self.cache[key]
+        return self.global_cache.get(key)
+
+    # ---- gluon trees
     def tree(self, t):
-        if t.key in self.tree_var:
-            return self.tree_var[t.key]
+        key = "T:" + t.key
+        v = self.lookup(key)
+        if v:
+            return v
         if t.kind == "leaf":
             name = f"w.e{bits(t.mask)[0]}"
-            self.tree_var[t.key] = name
+            self.global_cache[key] = name
             return name
         kids = [self.tree(k) for k in t.kids]
         self.iP_needed.add(t.mask)
@@ -282,63 +332,164 @@ class Emitter:
             for k in t.kids:
                 self.P_needed.add(k.mask)
             name = self.var("c")
-            self.lines.append(
-                f"const v4<T> {name} = vvv({kids[0]}, k.P{t.kids[0].mask}, {kids[1]}, k.P{t.kids[1].mask}, "
-                f"c.g * k.iP{t.mask});")
+            self.emit(f"const v4<T> {name} = vvv({kids[0]}, k.P{t.kids[0].mask}, {kids[1]}, "
+                      f"k.P{t.kids[1].mask}, c.g * k.iP{t.mask});")
             self.counts["vvv"] += 1
-            self.tree_var[t.key] = name
+            self.cache[key] = name
             return name
-        # four-gluon vertex: emit all three pieces together
-        base = f"v4({','.join(k.key for k in t.kids)})"
         q = self.var("c")
-        names = {p: f"{q}.{p}" for p in "ABC"}
-        self.lines.append(
-            f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, c.g2 * k.iP{t.mask});")
+        self.emit(f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, c.g2 * k.iP{t.mask});")
         self.counts["vvvv"] += 1
+        inner = ",".join(k.key for k in t.kids)
         for p in "ABC":
-            self.tree_var[f"{base.replace('v4', 'v4' + p, 1)}"] = names[p]
-        return self.tree_var[t.key]
+            self.cache[f"T:v4{p}({inner})"] = f"{q}.{p}"
+        return self.cache[key]
 
+    # ---- top line currents
+    def L(self, seq):
+        """Row current ubar Gamma(T1) S Gamma(T2) S ... Gamma(Tj) S."""
+        if not seq:
+            return "w.ub"
+        key = "L:" + "|".join(t.key for t in seq)
+        v = self.lookup(key)
+        if v:
+            return v
+        prev = self.L(seq[:-1])
+        cur = self.tree(seq[-1])
+        mask = 0
+        for t in seq:
+            mask |= t.mask
+        self.qL_needed.add(mask)
+        self.P_needed.add(mask)
+        name = self.var("l")
+        self.emit(f"const sp<T> {name} = ffv_row({prev}, {cur}, k.pt - k.P{mask}, k.mt, c.gk * k.iqL{mask});")
+        self.counts["ffv_row"] += 1
+        glob = self.global_leaf_lr and len(seq) == 1 and seq[0].kind == "leaf"
+        (self.global_cache if glob else self.cache)[key] = name
+        return name
+
+    def R(self, seq):
+        """Column current S Gamma(T1) S Gamma(T2) ... Gamma(Tk) v."""
+        if not seq:
+            return "w.v"
+        key = "R:" + "|".join(t.key for t in seq)
+        v = self.lookup(key)
+        if v:
+            return v
+        nxt = self.R(seq[1:])
+        cur = self.tree(seq[0])
+        mask = 0
+        for t in seq:
+            mask |= t.mask
+        self.qR_needed.add(mask)
+        self.P_needed.add(mask)
+        name = self.var("r")
+        self.emit(f"const sp<T> {name} = ffv_col({cur}, {nxt}, k.P{mask} - k.ptb, k.mt, c.gk * k.iqR{mask});")
+        self.counts["ffv_col"] += 1
+        glob = self.global_leaf_lr and len(seq) == 1 and seq[0].kind == "leaf"
+        (self.global_cache if glob else self.cache)[key] = name
+        return name
+
+    def tt_current(self):
+        v = self.global_cache.get("Jtt")
+        if v:
+            return v
+        self.iP_needed.add(self.full)
+        self.emit(f"const v4<T> jtt = tt_current(w.ub, w.v, c.gk * k.iP{self.full});")
+        self.counts["tt_current"] += 1
+        self.global_cache["Jtt"] = "jtt"
+        return "jtt"
+
+    # ---- amplitudes
     def accumulate(self, amp, seq):
         col = diagram_colour(seq)
         for w, c in sorted(col.items(), key=lambda x: self.flow_index[x[0]]):
             assert c in (1, -1), (seq, w, c)
             j = self.flow_index[w]
             op = "+" if c > 0 else "-"
-            self.lines.append(f"J[{j}] = J[{j}] {op} {amp};")
+            self.emit(f"J[{j}] = J[{j}] {op} {amp};")
             self.n_jterms += 1
 
-    def top_line(self, row, covered, seq):
-        rest = self.full ^ covered
-        # closures first: one tree over everything that is left
-        for t in trees(rest):
-            cur = self.tree(t)
+    def close_ttg(self, seq, j):
+        left, right = self.L(seq[:j]), self.R(seq[j + 1:])
+        cur = self.tree(seq[j])
+        a = self.var("a")
+        self.emit(f"const cx<T> {a} = ffv_amp({left}, {cur}, {right}, c.gk);")
+        self.counts["ffv_amp"] += 1
+        self.n_amp += 1
+        self.accumulate(a, seq)
+
+    def close_root(self, seq):
+        t = seq[0]
+        jtt = self.tt_current()
+        kids = [self.tree(k) for k in t.kids]
+        if t.kind == "v3":
+            for k in t.kids:
+                self.P_needed.add(k.mask)
             a = self.var("a")
-            self.lines.append(f"const cx<T> {a} = ffv_amp({row}, {cur}, w.v, c.gk);")
-            self.counts["ffv_amp"] += 1
+            self.emit(f"const cx<T> {a} = dot({jtt}, vvv({kids[0]}, k.P{t.kids[0].mask}, {kids[1]}, "
+                      f"k.P{t.kids[1].mask}, c.g));")
+            self.counts["vvv_amp"] += 1
             self.n_amp += 1
-            self.accumulate(a, seq + (t,))
-        # extensions
-        for s in sorted(submasks(rest)):
-            if s == rest:
-                continue
-            for t in trees(s):
-                cur = self.tree(t)
-                nxt = covered | s
-                self.q_needed.add(nxt)
-                name = self.var("f")
-                self.lines.append(
-                    f"const sp<T> {name} = ffv_row({row}, {cur}, k.q{nxt}, k.mt, c.gk * k.iq{nxt});")
-                self.counts["ffv_row"] += 1
-                self.top_line(name, nxt, seq + (t,))
+            self.accumulate(a, seq)
+            return
+        inner = ",".join(k.key for k in t.kids)
+        rkey = f"ROOT4:{inner}"
+        q = self.cache.get(rkey)
+        if q is None:
+            q = self.var("c")
+            self.emit(f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, c.g2);")
+            self.counts["vvvv_amp"] += 1
+            self.cache[rkey] = q
+        a = self.var("a")
+        self.emit(f"const cx<T> {a} = dot({jtt}, {q}.{t.piece});")
+        self.n_amp += 1
+        self.accumulate(a, seq)
 
     def program(self):
-        self.top_line("w.ub", 0, ())
+        diags = diagrams(self.ng)
+        groups = {}
+        leaf = []
+        for seq in diags:
+            kind, U, j = closing(seq)
+            if kind == "leaf":
+                leaf.append((seq, j))
+            else:
+                groups.setdefault(U, []).append((kind, seq, j))
+        # single-gluon row/column currents and the t tbar current are shared
+        # leaf-only diagrams: iterate over the column side first
+        leaf.sort(key=lambda x: ([t.key for t in x[0][x[1] + 1:]], [t.key for t in x[0]]))
+        self.emit("// leaf-only diagrams")
+        for seq, j in leaf:
+            self.close_ttg(seq, j)
+        self.cache = {}
+        for U in sorted(groups, key=lambda m: (popcount(m), m)):
+            items = groups[U]
+            order = {t.key: i for i, t in enumerate(trees(U))}
+
+            def anchor(it):
+                kind, seq, j = it
+                if kind == "ttg":
+                    return order[seq[j].key]
+                kids = seq[0].kids
+                ks = [popcount(k.mask) for k in kids]
+                return order[kids[ks.index(max(ks))].key]
+
+            items.sort(key=lambda it: (anchor(it), it[0], [t.key for t in it[1]]))
+            self.emit("MGRW_SCHED_BARRIER();")
+            self.emit(f"// closing trees over gluons {bits(U)}")
+            for kind, seq, j in items:
+                if kind == "ttg":
+                    self.close_ttg(seq, j)
+                else:
+                    self.close_root(seq)
+            self.cache = {}
         return self.lines
 
 
 def emit_process(name, ng):
     """C++ source of the process struct for g g -> t tbar + (ng-2) g."""
+    from math import factorial, gcd
     em = Emitter(ng)
     body = em.program()
     K = len(em.flows)
@@ -347,20 +498,20 @@ def emit_process(name, ng):
     den = 1
     for row in cf:
         for x in row:
-            den = den * x.denominator // __import__("math").gcd(den, x.denominator)
+            den = den * x.denominator // gcd(den, x.denominator)
     num = [[int(x * den) for x in row] for row in cf]
 
     P_masks = sorted(em.P_needed)
     iP_masks = sorted(em.iP_needed)
-    q_masks = sorted(em.q_needed)
+    qL_masks = sorted(em.qL_needed)
+    qR_masks = sorted(em.qR_needed)
 
     out = []
     w = out.append
     w(f"// Generated by paper_2312_07440_amd/gen/process.py -- g g -> t tbar + {ng - 2} g.")
     w(f"// {n_diagrams(ng)} Feynman diagrams, {K} colour flows, {1 << next_} helicity configurations.")
-    w(f"// Per helicity: {em.counts['vvv']} three-gluon currents, {em.counts['vvvv']} four-gluon vertices,")
-    w(f"// {em.counts['ffv_row']} top-line currents, {em.counts['ffv_amp']} closing vertices, "
-      f"{em.n_jterms} colour-flow accumulations.")
+    w("// Per helicity: " + ", ".join(f"{v} {k}" for k, v in em.counts.items()) +
+      f", {em.n_amp} amplitudes, {em.n_jterms} colour-flow accumulations.")
     w("#pragma once")
     w('#include "../mgrw_lorentz.h"')
     w("namespace mgrw {")
@@ -371,17 +522,21 @@ def emit_process(name, ng):
     w(f"  static constexpr int NHEL = {1 << next_};")
     w(f"  static constexpr int NDIAG = {n_diagrams(ng)};")
     w(f"  static constexpr int CF_DEN = {den};")
-    from math import factorial
     w(f"  static constexpr double NORM = 1.0 / (4.0 * 64.0 * {factorial(ng - 2)}.0 * {den}.0);")
+    w("  // Helicity-independent kinematics of one event: incoming momentum sums of")
+    w("  // gluon sets, the top and antitop momenta, and inverse propagator")
+    w("  // denominators formed in double precision.")
     w("  template <typename T> struct kin {")
     w("    T mt;")
+    w("    r4<T> pt, ptb;")
     for m in P_masks:
         w(f"    r4<T> P{m};")
     for m in iP_masks:
         w(f"    T iP{m};")
-    for m in q_masks:
-        w(f"    r4<T> q{m};")
-        w(f"    T iq{m};")
+    for m in qL_masks:
+        w(f"    T iqL{m};")
+    for m in qR_masks:
+        w(f"    T iqR{m};")
     w("  };")
     w("  template <typename T> struct basis {")
     for i in range(ng):
@@ -393,16 +548,16 @@ def emit_process(name, ng):
         w(f"    pol4<T> e{i};")
     w("    sp<T> ub, v;")
     w("  };")
-    # kinematics in double
-    w("  // Helicity-independent kinematics, in double precision, rounded to T once.")
     w("  template <typename T, typename P>")
     w("  static MGRW_HD void kinematics(const P& p, double mt, kin<T>& k) {")
     w("    k.mt = T(mt);")
+    w("    k.pt = {T(p[2][0]), T(p[2][1]), T(p[2][2]), T(p[2][3])};")
+    w("    k.ptb = {T(p[3][0]), T(p[3][1]), T(p[3][2]), T(p[3][3])};")
     w("    double kin_in[NG][4];")
     for i, ip in enumerate(GLUON_PARTICLE[:ng]):
         sgn = "" if ip < 2 else "-"
         w(f"    for (int m = 0; m < 4; ++m) kin_in[{i}][m] = {sgn}p[{ip}][m];")
-    allm = sorted(set(P_masks) | set(iP_masks) | set(q_masks))
+    allm = sorted(set(P_masks) | set(iP_masks) | set(qL_masks) | set(qR_masks))
     for m in allm:
         terms = " + ".join(f"kin_in[{i}][m]" for i in bits(m))
         w(f"    double S{m}[4]; for (int m = 0; m < 4; ++m) S{m}[m] = {terms};")
@@ -411,12 +566,13 @@ def emit_process(name, ng):
     for m in iP_masks:
         w(f"    k.iP{m} = T(1.0 / (((S{m}[0] * S{m}[0] - S{m}[1] * S{m}[1]) - S{m}[2] * S{m}[2]) - "
           f"S{m}[3] * S{m}[3]));")
-    for m in q_masks:
+    for m in qL_masks:
         w(f"    {{ double q[4]; for (int m = 0; m < 4; ++m) q[m] = p[2][m] - S{m}[m];")
-        w(f"      k.q{m} = {{T(q[0]), T(q[1]), T(q[2]), T(q[3])}};")
-        w(f"      k.iq{m} = T(1.0 / ((((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1]) - q[2] * q[2]) - mt * mt)); }}")
+        w(f"      k.iqL{m} = T(1.0 / ((((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1]) - q[2] * q[2]) - mt * mt)); }}")
+    for m in qR_masks:
+        w(f"    {{ double q[4]; for (int m = 0; m < 4; ++m) q[m] = S{m}[m] - p[3][m];")
+        w(f"      k.iqR{m} = T(1.0 / ((((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1]) - q[2] * q[2]) - mt * mt)); }}")
     w("  }")
-    # external basis
     w("  template <typename T, typename P>")
     w("  static MGRW_HD void external_basis(const P& p, double mt, basis<T>& b) {")
     for i, ip in enumerate(GLUON_PARTICLE[:ng]):
@@ -424,25 +580,23 @@ def emit_process(name, ng):
     w("    b.t = make_fermion_basis<T>(p[2], mt);")
     w("    b.tb = make_fermion_basis<T>(p[3], mt);")
     w("  }")
-    # helicity selection: bit (NEXT-1-i) of h is particle i (1 = +)
-    w("  template <typename T>")
-    w("  static MGRW_HD void external(const basis<T>& b, int h, ext<T>& w) {")
+    w("  template <typename T, typename B>")
+    w("  static MGRW_HD void external(const B& b, int h, ext<T>& w) {")
     for i, ip in enumerate(GLUON_PARTICLE[:ng]):
         out_flag = "true" if ip >= 2 else "false"
-        w(f"    w.e{i} = gluon_pol(b.g{i}, (h >> {next_ - 1 - ip}) & 1 ? 1 : -1, {out_flag});")
-    w(f"    w.ub = ubar_out(b.t, (h >> {next_ - 1 - 2}) & 1 ? 1 : -1);")
-    w(f"    w.v = v_out(b.tb, (h >> {next_ - 1 - 3}) & 1 ? 1 : -1);")
+        w(f"    w.e{i} = gluon_pol<T>(b.g{i}, (h >> {next_ - 1 - ip}) & 1 ? 1 : -1, {out_flag});")
+    w(f"    w.ub = ubar_out<T>(b.t, (h >> {next_ - 1 - 2}) & 1 ? 1 : -1);")
+    w(f"    w.v = v_out<T>(b.tb, (h >> {next_ - 1 - 3}) & 1 ? 1 : -1);")
     w("  }")
     w("  template <typename T> struct coup { T g, g2, gk; };")
-    w("  // Colour-flow amplitudes J (times g^0 phases dropped) of one helicity.")
-    w("  template <typename T>")
-    w("  static MGRW_HD void amplitude(const ext<T>& w, const kin<T>& k, const coup<T>& c, cx<T>* J) {")
+    w("  // Colour-flow amplitudes J of one helicity (common phase dropped).")
+    w("  // k: the event's kin<T> (in registers or in LDS).")
+    w("  template <typename T, typename KN>")
+    w("  static MGRW_HD void amplitude(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {")
     w("    for (int i = 0; i < K; ++i) J[i] = {T(0), T(0)};")
     for line in body:
         w("    " + line)
     w("  }")
-    # colour sum with exact integer numerators
-    w(f"  // sum_ij CF_ij Re(conj(J_i) J_j) * CF_DEN, symmetric form.")
     w("  template <typename T>")
     w("  static MGRW_HD T colour_sum(const cx<T>* J) {")
     w("    T s = T(0);")
