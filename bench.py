@@ -50,6 +50,40 @@ def cpu_baseline(proc, ng, mom_np, kap, gpu_out, sample, points_per_event):
                       f"({dt:.1f} s wall)"}, float(err.max()), float(np.median(err))
 
 
+def surrogate_leg(args, proc, mom, exact_out, kap, torch, generate_events):
+    """Train the MLP on disjoint events, then time the audited surrogate
+    reweight of the same batch; error measured against the exact weights."""
+    log(f"surrogate: generating {args.train_events} training events")
+    train = torch.from_numpy(generate_events(args.proc, args.train_events, first_event=1 << 26)).to(mom.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = proc.train_surrogate(train, epochs=args.epochs, batch=16384, lr=2e-3, lr_decay=0.7, seed=3003)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"surrogate: trained in {t_train:.1f}s, losses {losses}")
+    del train
+    sout = torch.empty_like(exact_out)
+    proc.reweight_surrogate(mom, out=sout, audit_fraction=args.audit, seed=7, max_audit_error=1.0)
+    torch.cuda.synchronize()
+    times, stats, fb = [], None, False
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        _, stats, fb = proc.reweight_surrogate(mom, out=sout, audit_fraction=args.audit, seed=7 + i,
+                                               max_audit_error=0.01)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = 1e3 * float(np.mean(times))
+    err = torch.abs(sout / exact_out - 1.0)
+    e_mean = float(err.mean())
+    e_p99 = float(torch.quantile(err.flatten()[:: max(1, err.numel() // 4000000)].float(), 0.99))
+    return {"value": args.n * args.points / (ms * 1e-3), "unit": "events*points/s", "ms_per_step": ms,
+            "mean_abs_weight_err": e_mean, "p99_abs_weight_err": e_p99, "audit_fraction": args.audit,
+            "audit_mean_err_estimate": float(np.mean(stats[:, 2])), "fell_back": bool(fb),
+            "train_events": args.train_events, "epochs": args.epochs, "train_seconds": t_train,
+            "final_loss": float(losses[-1]),
+            "timing": "host wall clock per call (the call synchronises once for the audit statistics)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +95,10 @@ def main():
     ap.add_argument("--points", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--train-events", type=int, default=1 << 21)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--audit", type=float, default=0.01)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the reweighting is embarrassingly parallel over events and "
@@ -127,6 +165,8 @@ def main():
                      "frac": achieved / peak, "traffic": None,
                      "flops_per_event": fpe, "per_helicity_flops": fcounts["per_helicity_flops"]},
     }
+    if not args.no_surrogate:
+        res["surrogate"] = surrogate_leg(args, proc, mom, out, kap, torch, generate_events)
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, args.n)
         log(f"cpu baseline: oracle on {sample} events")

@@ -130,6 +130,78 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
  * unaffected: its parameters travelled with the launch. */
 void mgrw_destroy_process(mgrw_process *p);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the reweight factor.
+ *
+ * A multilayer perceptron predicts y = log(|M_k|^2 / |M_base|^2) for an event
+ * and a parameter point k: inputs are the 24 momentum components of the
+ * event divided by sqrt(s)/2, kt = (kappa_k - 1)/0.2, and for the 14 particle
+ * pairs other than the two beams v = 2 p_i.p_j / s and log v
+ * (MGRW_SURROGATE_N_FEATURES = 53 values); four hidden layers of
+ * 256 SiLU units (bfloat16 weights, float32 accumulation on the matrix
+ * cores); the output is yhat = (kappa_k - 1) * h, h the last linear unit, so
+ * the prediction is exact at kappa = 1.  Surrogate weights W~' = W exp(yhat).
+ * A random audit subset of events is evaluated exactly (eq. (3)) and serves
+ * as a control variate for the sums of weights.  QCD processes only; the
+ * points must differ from the base only in kappa_ttg.
+ *
+ * Parameters (float32, MGRW_SURROGATE_N_PARAMS values) in this order:
+ * W1[256][64] (input columns 53..63 unused, zero), b1[256], W2[256][256],
+ * b2[256], W3[256][256], b3[256], W4[256][256], b4[256], w5[256], b5[1];
+ * W[out][in].
+ * ------------------------------------------------------------------------ */
+
+#define MGRW_SURROGATE_N_PARAMS 214273
+#define MGRW_SURROGATE_N_FEATURES 53
+
+typedef struct {
+    int32_t epochs;      /* passes over the training samples                     */
+    int32_t batch;       /* samples (event, point) per Adam step, multiple of 64 */
+    double lr;           /* Adam step size                                       */
+    double lr_decay;     /* step-size factor applied after each epoch            */
+    uint64_t seed;       /* initialisation and shuffling                         */
+} mgrw_train_config;
+
+/* Train the surrogate on n_events events (device momenta as for
+ * mgrw_reweight) at the handle's current points: the exact kernels label every
+ * (event, point) pair, then the network is fitted by mean-squared error with
+ * Adam, all on the device.  A previous network is replaced, starting from a
+ * seeded initialisation.  loss_out (host, may be NULL) receives the mean
+ * training loss of each epoch.  Synchronous.  Errors: MGRW_ERR_ARG,
+ * MGRW_ERR_UNSUPPORTED (e+e- process, or points that change more than
+ * kappa_ttg), MGRW_ERR_STATE (no points), MGRW_ERR_DEVICE, MGRW_ERR_ALLOC. */
+mgrw_status mgrw_surrogate_train(mgrw_process *p, const double *mom, int64_t n_events,
+                                 const mgrw_train_config *cfg, double *loss_out, void *stream);
+
+/* Reweight with the surrogate and an exact audit.  Every event gets
+ * w_out[k*n_events + e] = W_e exp(yhat); events selected by the audit (a
+ * counter-based hash of (seed, e) below audit_fraction, in (0, 1]) are
+ * evaluated exactly and receive the exact W'.  audit_stats (host,
+ * [n_points][5], may be NULL) receives per point: the control-variate estimate
+ * of sum_e W'_e (surrogate sum + (exact - surrogate) summed over the audit /
+ * audit_fraction), the surrogate sum, the audited mean |W~'/W' - 1|, its
+ * standard error, and the number of audited events.  If the audited mean
+ * error of any point exceeds max_audit_error the whole batch is recomputed
+ * exactly and *fell_back (may be NULL) is set to 1.  Synchronises once.
+ * Errors: as mgrw_reweight; MGRW_ERR_STATE if no surrogate is trained. */
+mgrw_status mgrw_reweight_surrogate(mgrw_process *p, const double *mom, const double *w_in, int64_t n_events,
+                                    double audit_fraction, uint64_t seed, double max_audit_error,
+                                    double *w_out, double *audit_stats, int *fell_back, void *stream);
+
+/* Copy the surrogate parameters to / from a host float array of
+ * MGRW_SURROGATE_N_PARAMS values (checkpointing, tests).  _get needs a
+ * trained or loaded surrogate (MGRW_ERR_STATE otherwise); _set creates one. */
+mgrw_status mgrw_surrogate_get(const mgrw_process *p, float *params);
+mgrw_status mgrw_surrogate_set(mgrw_process *p, const float *params);
+
+/* One forward and backward pass over m given samples (device arrays):
+ * x[m][MGRW_SURROGATE_N_FEATURES] features, kd[m] = kappa - 1, y[m] targets; pred[m] (device)
+ * receives yhat, grad (host, MGRW_SURROGATE_N_PARAMS floats) the gradient of
+ * the mean squared error, loss (host) its value.  m is a multiple of 64.
+ * The same kernels as training.  Errors: MGRW_ERR_ARG, MGRW_ERR_STATE. */
+mgrw_status mgrw_surrogate_fwd_bwd(mgrw_process *p, const float *x, const float *kd, const float *y, int64_t m,
+                                   float *pred, float *grad, double *loss, void *stream);
+
 /* Text describing the calling thread's last non-OK status ("" if none). */
 const char *mgrw_last_error(void);
 

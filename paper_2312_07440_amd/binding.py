@@ -40,6 +40,16 @@ def make_params(**kw):
     return Params(**d)
 
 
+class TrainConfig(ctypes.Structure):
+    """mgrw_train_config."""
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("lr_decay", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+SURROGATE_N_PARAMS = 214273
+SURROGATE_N_FEATURES = 53
+
+
 class MgrwError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"mgrw status {status}: {msg}")
@@ -74,6 +84,18 @@ def lib():
     L.mgrw_destroy_process.restype = None
     L.mgrw_last_error.argtypes = []
     L.mgrw_last_error.restype = ctypes.c_char_p
+    L.mgrw_surrogate_train.argtypes = [vp, dp, i64, ctypes.POINTER(TrainConfig), ctypes.POINTER(ctypes.c_double), vp]
+    L.mgrw_surrogate_train.restype = ctypes.c_int
+    L.mgrw_reweight_surrogate.argtypes = [vp, dp, dp, i64, ctypes.c_double, ctypes.c_uint64, ctypes.c_double, dp,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), vp]
+    L.mgrw_reweight_surrogate.restype = ctypes.c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.mgrw_surrogate_get.argtypes = [vp, fp]
+    L.mgrw_surrogate_get.restype = ctypes.c_int
+    L.mgrw_surrogate_set.argtypes = [vp, fp]
+    L.mgrw_surrogate_set.restype = ctypes.c_int
+    L.mgrw_surrogate_fwd_bwd.argtypes = [vp, vp, vp, vp, i64, vp, fp, ctypes.POINTER(ctypes.c_double), vp]
+    L.mgrw_surrogate_fwd_bwd.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -96,6 +118,15 @@ def _ptr(t, name, n=None, dtype=None, allow_none=False):
         raise ValueError(f"{name} must be float64")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _fptr(t, name, n=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
     if n is not None and t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
     return ctypes.c_void_p(t.data_ptr())
@@ -162,3 +193,59 @@ class Process:
                                   _ptr(out, "out", self.n_points * n),
                                   _ptr(me_base_out, "me_base_out", n, allow_none=True), _stream(stream)))
         return out
+
+    # ---------------------------------------------------------- surrogate
+
+    def train_surrogate(self, mom, epochs=10, batch=16384, lr=1e-3, lr_decay=0.8, seed=3003):
+        """Label with the exact kernels and fit the MLP; returns per-epoch losses."""
+        import numpy as np
+        n = self._n(mom)
+        cfg = TrainConfig(int(epochs), int(batch), float(lr), float(lr_decay), int(seed))
+        losses = np.zeros(int(epochs))
+        check(lib().mgrw_surrogate_train(self._h, _ptr(mom, "mom"), n, ctypes.byref(cfg),
+                                         losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(None)))
+        return losses
+
+    def reweight_surrogate(self, mom, w_in=None, audit_fraction=0.01, seed=2002, max_audit_error=0.01,
+                           out=None, stream=None):
+        """Returns (w_out [n_points, n], stats [n_points, 5], fell_back)."""
+        import numpy as np
+        import torch
+        n = self._n(mom)
+        if out is None:
+            out = torch.empty((self.n_points, n), dtype=torch.float64, device=mom.device)
+        stats = np.zeros((self.n_points, 5))
+        fb = ctypes.c_int(0)
+        check(lib().mgrw_reweight_surrogate(self._h, _ptr(mom, "mom"), _ptr(w_in, "w_in", n, allow_none=True), n,
+                                            float(audit_fraction), int(seed), float(max_audit_error),
+                                            _ptr(out, "out", self.n_points * n),
+                                            stats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            ctypes.byref(fb), _stream(stream)))
+        return out, stats, bool(fb.value)
+
+    def surrogate_params(self):
+        import numpy as np
+        out = np.zeros(SURROGATE_N_PARAMS, dtype=np.float32)
+        check(lib().mgrw_surrogate_get(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def set_surrogate_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != SURROGATE_N_PARAMS:
+            raise ValueError("wrong number of parameters")
+        check(lib().mgrw_surrogate_set(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def surrogate_fwd_bwd(self, x, kd, y, stream=None):
+        """One forward/backward pass on device float32 x [m, 53], kd [m], y [m]."""
+        import numpy as np
+        import torch
+        m = x.shape[0]
+        pred = torch.empty(m, dtype=torch.float32, device=x.device)
+        grad = np.zeros(SURROGATE_N_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double(0.0)
+        check(lib().mgrw_surrogate_fwd_bwd(self._h, _fptr(x, "x", m * SURROGATE_N_FEATURES), _fptr(kd, "kd", m), _fptr(y, "y", m), m,
+                                           _fptr(pred, "pred", m),
+                                           grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                           ctypes.byref(loss), _stream(stream)))
+        return pred, grad, loss.value

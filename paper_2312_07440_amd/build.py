@@ -42,7 +42,7 @@ def build(verbose=False, jobs=None):
     from .gen import generate, QCD_PROCESSES
     generate()
     os.makedirs(OBJ, exist_ok=True)
-    units = [os.path.join(CSRC, "mgrw_abi.hip")] + [os.path.join(GEN, f"qcd_{p}.hip") for p in QCD_PROCESSES]
+    units = [os.path.join(CSRC, "mgrw_abi.hip"), os.path.join(CSRC, "mgrw_mlp.hip")] + [os.path.join(GEN, f"qcd_{p}.hip") for p in QCD_PROCESSES]
     objs = [os.path.join(OBJ, os.path.basename(u).replace(".hip", ".o")) for u in units]
     jobs = jobs or min(len(units), os.cpu_count() or 4)
     with ThreadPoolExecutor(jobs) as ex:

@@ -15,6 +15,7 @@
 #include <string>
 
 #include "../../include/mgrw.h"
+#include "mgrw_internal.h"
 #include "mgrw_kernels.h"
 #include "gen/gg_tt.inc"
 #include "gen/gg_ttg.inc"
@@ -67,13 +68,6 @@ bool finite(double x) { return std::isfinite(x); }
 
 }  // namespace
 
-struct mgrw_process {
-    int proc;
-    int prec;
-    mgrw_params base;
-    mgrw_params points[MGRW_MAX_POINTS];
-    int n_points;
-};
 
 namespace {
 
@@ -201,6 +195,7 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     p->prec = prec;
     p->base = *base;
     p->n_points = 0;
+    p->sur = nullptr;
     *out = p;
     return MGRW_OK;
 }
@@ -250,8 +245,14 @@ mgrw_status mgrw_process_info(const mgrw_process* p, int* n_ext, int* n_flows, i
     return MGRW_OK;
 }
 
-void mgrw_destroy_process(mgrw_process* p) { delete p; }
+void mgrw_destroy_process(mgrw_process* p) {
+    if (!p) return;
+    mgrw::surrogate_destroy(p->sur);
+    delete p;
+}
 
 const char* mgrw_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+mgrw_status mgrw::set_error(mgrw_status code, const std::string& msg) { return fail(code, msg); }

@@ -1,0 +1,21 @@
+// Internal declarations shared by the translation units of libmgrw.
+#pragma once
+
+#include <string>
+
+#include "../../include/mgrw.h"
+
+namespace mgrw {
+struct surrogate;                       // MLP state (mgrw_mlp.hip)
+void surrogate_destroy(surrogate* s);
+mgrw_status set_error(mgrw_status code, const std::string& msg);
+}  // namespace mgrw
+
+struct mgrw_process {
+    int proc;
+    int prec;
+    mgrw_params base;
+    mgrw_params points[MGRW_MAX_POINTS];
+    int n_points;
+    mgrw::surrogate* sur;               // null until trained or loaded
+};

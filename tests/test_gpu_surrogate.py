@@ -1,0 +1,177 @@
+"""GPU tests of the learned surrogate (MFMA kernels) through the C ABI.
+
+* forward/backward of the device network against the FP64 oracle network,
+  both with the oracle emulating the bfloat16 rounding points (float32
+  accumulation differences only) and in plain FP64 (bfloat16 noise);
+* training lowers the loss;
+* surrogate reweighting: audited events carry the exact weights, the
+  control-variate statistics follow from the surrogate and exact weights,
+  the fallback reproduces the exact path;
+* what the network gains over the method without it.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from synth import generate_events, kappa_points
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def dev(torch, a, dt=None):
+    return torch.from_numpy(np.ascontiguousarray(a if dt is None else a.astype(dt))).to("cuda:0")
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def tensor_slices():
+    out, o = {}, 0
+    for name, shape in mlp.SIZES:
+        n = int(np.prod(shape))
+        out[name] = slice(o, o + n)
+        o += n
+    return out
+
+
+def test_fwd_bwd_parity(torch_dev):
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    say("case surrogate fwd/bwd parity m=1024")
+    rng = np.random.default_rng(11)
+    m = 1024
+    params = mlp.init_params(9).astype(np.float32)
+    x = rng.uniform(-1, 1, (m, mlp.NFEAT)).astype(np.float32)
+    kd = rng.uniform(-0.2, 0.2, m).astype(np.float32)
+    y = rng.normal(0, 0.2, m).astype(np.float32)
+    p = mg.Process("gg_ttgg", "mixed")
+    p.set_surrogate_params(params)
+    assert np.array_equal(p.surrogate_params(), params)
+    pred, grad, loss = p.surrogate_fwd_bwd(dev(torch, x), dev(torch, kd), dev(torch, y))
+    torch.cuda.synchronize()
+    p64 = params.astype(np.float64)
+    lo_e, yh_e, g_e = mlp.loss_and_grad(p64, x.astype(np.float64), kd.astype(np.float64), y.astype(np.float64),
+                                        emulate_bf16=True)
+    lo_p, yh_p, g_p = mlp.loss_and_grad(p64, x.astype(np.float64), kd.astype(np.float64), y.astype(np.float64))
+    pr = pred.cpu().numpy()
+    say(f"  pred rel-L2 vs bf16-emulating oracle {rel_l2(pr, yh_e):.2e}, vs FP64 {rel_l2(pr, yh_p):.2e}; "
+        f"loss {loss:.6e} vs {lo_e:.6e}")
+    # float32 vs float64 pre-activations round to different bfloat16 values for
+    # a fraction phi ~ 1e-3 of activations near a rounding boundary: a relative
+    # L2 difference of about 2^-8 sqrt(phi) ~ 1e-4 per stored tensor.
+    assert rel_l2(pr, yh_e) < 1e-3
+    assert abs(loss / lo_e - 1) < 1e-4
+    assert rel_l2(pr, yh_p) < 3e-2
+    for name, sl in tensor_slices().items():
+        e_em, e_64 = rel_l2(grad[sl], g_e[sl]), rel_l2(grad[sl], g_p[sl])
+        say(f"  grad {name}: rel-L2 {e_em:.2e} (emulated bf16), {e_64:.2e} (FP64)")
+        assert e_em < 5e-3, name
+        assert e_64 < 6e-2, name
+
+
+@pytest.fixture(scope="module")
+def trained_ttg(torch_dev):
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    say("case surrogate training gg_ttg 16384 events x 8 points")
+    kap = kappa_points(8)
+    p = mg.Process("gg_ttg", "mixed")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    mom = dev(torch, generate_events("gg_ttg", 16384, first_event=10 ** 6))
+    losses = p.train_surrogate(mom, epochs=4, batch=4096, lr=2e-3, lr_decay=0.7, seed=17)
+    say(f"  losses {losses}")
+    return p, losses
+
+
+def test_training_lowers_loss(trained_ttg):
+    _, losses = trained_ttg
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_audit_and_fallback(torch_dev, trained_ttg):
+    torch = torch_dev
+    p, _ = trained_ttg
+    n = 20000
+    say(f"case surrogate audit n={n}")
+    mom = dev(torch, generate_events("gg_ttg", n))
+    w = dev(torch, np.random.default_rng(2).uniform(0.5, 2.0, n))
+    exact = p.reweight(mom, w_in=w).cpu().numpy()
+    pure, st0, fb0 = p.reweight_surrogate(mom, w_in=w, audit_fraction=1e-12, seed=5, max_audit_error=1.0)
+    pure = pure.cpu().numpy()
+    assert not fb0 and np.all(st0[:, 4] == 0)
+    f = 0.05
+    out, st, fb = p.reweight_surrogate(mom, w_in=w, audit_fraction=f, seed=5, max_audit_error=1.0)
+    out = out.cpu().numpy()
+    torch.cuda.synchronize()
+    assert not fb
+    audited = np.all(out != pure, axis=0)
+    na = int(st[0, 4])
+    assert audited.sum() == na and abs(na - f * n) < 6 * np.sqrt(f * n)
+    assert np.array_equal(out[:, audited], exact[:, audited])
+    assert np.array_equal(out[:, ~audited], pure[:, ~audited])
+    ssur = pure.sum(axis=1)
+    d = (exact[:, audited] - pure[:, audited]).sum(axis=1)
+    err = np.abs(pure[:, audited] / exact[:, audited] - 1)
+    assert np.allclose(st[:, 1], ssur, rtol=1e-10)
+    assert np.allclose(st[:, 0], ssur + d / f, rtol=1e-10)
+    assert np.allclose(st[:, 2], err.mean(axis=1), rtol=1e-8)
+    assert np.allclose(st[:, 3], err.std(axis=1, ddof=1) / np.sqrt(na), rtol=1e-6)
+    # an impossible error bound forces the exact path
+    out2, _, fb2 = p.reweight_surrogate(mom, w_in=w, audit_fraction=f, seed=5, max_audit_error=0.0)
+    assert fb2
+    assert np.array_equal(out2.cpu().numpy(), exact)
+
+
+def test_surrogate_gain_over_network_free_method(torch_dev):
+    """(i) accuracy: mean |W~'/W' - 1| of the network vs the best predictor
+    without a network (a per-point constant log ratio); (ii) estimator
+    variance at equal exact budget: audit-only estimate (1/f) sum_A W' vs the
+    control variate with the network, over 32 audit seeds."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    kap = kappa_points(16)
+    say("case surrogate gain gg_ttgg: train 65536 events x 16 points")
+    p = mg.Process("gg_ttgg", "mixed")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    train = dev(torch, generate_events("gg_ttgg", 65536, first_event=2 * 10 ** 7))
+    losses = p.train_surrogate(train, epochs=6, batch=8192, lr=2e-3, lr_decay=0.7, seed=23)
+    ex_train = p.reweight(train).cpu().numpy()
+    const = np.log(ex_train).mean(axis=1)                    # per-point constant log ratio
+    n = 32768
+    mom = dev(torch, generate_events("gg_ttgg", n))
+    exact = p.reweight(mom).cpu().numpy()
+    pure, _, _ = p.reweight_surrogate(mom, audit_fraction=1e-12, seed=1, max_audit_error=1.0)
+    pure = pure.cpu().numpy()
+    e_net = np.mean(np.abs(pure / exact - 1))
+    e_const = np.mean(np.abs(np.exp(const)[:, None] / exact - 1))
+    f = 0.01
+    cv, ao = [], []
+    for s in range(32):
+        out, st, _ = p.reweight_surrogate(mom, audit_fraction=f, seed=100 + s, max_audit_error=1.0)
+        audited = np.all(out.cpu().numpy() != pure, axis=0)
+        cv.append(st[:, 0])
+        ao.append(exact[:, audited].sum(axis=1) / f)
+    cv, ao = np.array(cv), np.array(ao)
+    ratio = np.mean(np.var(ao, axis=0) / np.var(cv, axis=0))
+    truth = exact.sum(axis=1)
+    say(f"  losses {np.round(losses, 6)}; mean |W~'/W'-1|: network {e_net:.4f}, constant {e_const:.4f}; "
+        f"variance(audit only)/variance(control variate) = {ratio:.1f}; "
+        f"CV bias/sigma {np.mean((cv.mean(0) - truth) / (cv.std(0) / np.sqrt(32) + 1e-300)):.2f}")
+    assert e_net < 0.5 * e_const
+    assert ratio > 4.0
