@@ -23,6 +23,22 @@ PEAK_FP64_TFLOPS = 78.6
 HBM_TBS = 8.0
 
 
+# HBM traffic of the exact kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (copy-calibrated; see profiles/), valid only for the kernel sources it was
+# measured on: keyed by a fingerprint of those sources.
+MEASURED_TRAFFIC = {("gg_ttgg", "mixed", "e5f9ba7e41a2cd56"): 1794833.0}   # bytes per event per launch
+KERNEL_SOURCES = ["paper_2312_07440_amd/csrc/mgrw_kernels.h", "paper_2312_07440_amd/csrc/mgrw_lorentz.h",
+                  "paper_2312_07440_amd/csrc/mgrw_event.h", "paper_2312_07440_amd/gen/process.py"]
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(HERE, s), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -99,6 +115,8 @@ def main():
     ap.add_argument("--train-events", type=int, default=1 << 21)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--audit", type=float, default=0.01)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the reweighting is embarrassingly parallel over events and "
@@ -120,6 +138,12 @@ def main():
     out = torch.empty((args.points, args.n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(args.warmup):
         log(f"warmup {i}")
         proc.reweight(mom, out=out)
@@ -143,6 +167,8 @@ def main():
     achieved = fpe * args.n / (ms * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
     value = args.n * args.points / (ms * 1e-3)
+    tb = MEASURED_TRAFFIC.get((args.proc, args.prec, kernel_fingerprint()))
+    traffic = None if tb is None else tb * args.n
 
     res = {
         "metric": "reweighted events/s x16 param pts, gg->ttbar gg: exact vs surrogate at <=1% weight err",
@@ -162,7 +188,7 @@ def main():
                    "events": args.n, "points": args.points, "process": args.proc,
                    "precision": args.prec, "path": "exact"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "flops_per_event": fpe, "per_helicity_flops": fcounts["per_helicity_flops"]},
     }
     if not args.no_surrogate:

@@ -126,6 +126,18 @@ mgrw_status mgrw_reweight(mgrw_process *p, const double *mom, const double *w_in
 mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, int *n_hel,
                               int *n_diagrams);
 
+/* Options.  MGRW_OPT_LANE_MAPPING selects how events map onto the GPU's
+ * lanes for the exact QCD kernels: MGRW_MAP_AUTO (default),
+ * MGRW_MAP_EVENT_PER_LANE (one event per lane, helicities in a loop), or
+ * MGRW_MAP_EVENT_PER_WAVE (one event per 64-lane wave, helicity
+ * configurations on the lanes; processes with a multiple of 64 helicity
+ * configurations only).  Results agree to rounding.  Errors: MGRW_ERR_ARG
+ * (unknown option or value), MGRW_ERR_UNSUPPORTED (mapping not available for
+ * the process). */
+enum { MGRW_OPT_LANE_MAPPING = 1 };
+enum { MGRW_MAP_AUTO = 0, MGRW_MAP_EVENT_PER_LANE = 1, MGRW_MAP_EVENT_PER_WAVE = 2 };
+mgrw_status mgrw_set_option(mgrw_process *p, int option, int64_t value);
+
 /* Release the handle (NULL is ignored).  Work already launched with it is
  * unaffected: its parameters travelled with the launch. */
 void mgrw_destroy_process(mgrw_process *p);

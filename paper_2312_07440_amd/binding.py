@@ -96,6 +96,8 @@ def lib():
     L.mgrw_surrogate_set.restype = ctypes.c_int
     L.mgrw_surrogate_fwd_bwd.argtypes = [vp, vp, vp, vp, i64, vp, fp, ctypes.POINTER(ctypes.c_double), vp]
     L.mgrw_surrogate_fwd_bwd.restype = ctypes.c_int
+    L.mgrw_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
+    L.mgrw_set_option.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -170,6 +172,11 @@ class Process:
         arr = (Params * max(1, len(pts)))(*pts)
         check(lib().mgrw_set_params(self._h, arr, len(pts)))
         self.n_points = len(pts)
+
+    def set_lane_mapping(self, mapping):
+        """'auto', 'event_per_lane' or 'event_per_wave'."""
+        v = {"auto": 0, "event_per_lane": 1, "event_per_wave": 2}[mapping]
+        check(lib().mgrw_set_option(self._h, 1, v))
 
     def _n(self, mom):
         if mom.dim() != 3 or mom.shape[0] != self.n_ext or mom.shape[1] != 4:

@@ -165,6 +165,10 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
     a.npts = npts;
     a.mode = mode;
     a.mt = p->base.mt;
+    // automatic choice: one event per wave when the helicity configurations fill
+    // whole waves (kinematics then live in the scalar cache, not in VGPRs/LDS)
+    a.mapping = p->mapping != MGRW_MAP_AUTO ? p->mapping
+                : (info_of(p->proc).n_hel % 64 == 0 ? MGRW_MAP_EVENT_PER_WAVE : MGRW_MAP_EVENT_PER_LANE);
     const int fp64 = p->prec == MGRW_FP64;
     switch (p->proc) {
         case MGRW_GG_TT: return launched(launch_gg_tt(fp64, mom, w_in, n, a, out, me0, s));
@@ -195,6 +199,7 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     p->prec = prec;
     p->base = *base;
     p->n_points = 0;
+    p->mapping = MGRW_MAP_AUTO;
     p->sur = nullptr;
     *out = p;
     return MGRW_OK;
@@ -242,6 +247,17 @@ mgrw_status mgrw_process_info(const mgrw_process* p, int* n_ext, int* n_flows, i
     if (n_flows) *n_flows = i.n_flows;
     if (n_hel) *n_hel = i.n_hel;
     if (n_diagrams) *n_diagrams = i.n_diagrams;
+    return MGRW_OK;
+}
+
+mgrw_status mgrw_set_option(mgrw_process* p, int option, int64_t value) {
+    if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
+    if (option != MGRW_OPT_LANE_MAPPING) return fail(MGRW_ERR_ARG, "unknown option");
+    if (value != MGRW_MAP_AUTO && value != MGRW_MAP_EVENT_PER_LANE && value != MGRW_MAP_EVENT_PER_WAVE)
+        return fail(MGRW_ERR_ARG, "unknown lane mapping");
+    if (value == MGRW_MAP_EVENT_PER_WAVE && (p->proc == MGRW_EE_MUMU || info_of(p->proc).n_hel % 64 != 0))
+        return fail(MGRW_ERR_UNSUPPORTED, "one event per wave needs a multiple of 64 helicity configurations");
+    p->mapping = int(value);
     return MGRW_OK;
 }
 

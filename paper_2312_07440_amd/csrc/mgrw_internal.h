@@ -17,5 +17,6 @@ struct mgrw_process {
     mgrw_params base;
     mgrw_params points[MGRW_MAX_POINTS];
     int n_points;
+    int mapping;                        // MGRW_MAP_*
     mgrw::surrogate* sur;               // null until trained or loaded
 };

@@ -21,6 +21,7 @@ struct qcd_launch {
     int npts;        // points in pts (base first)
     int mode;        // 0: reweight, 1: |M|^2 of pts[0] only
     double mt;
+    int mapping;     // MGRW_MAP_EVENT_PER_LANE or MGRW_MAP_EVENT_PER_WAVE
 };
 
 struct ew_launch {
@@ -104,11 +105,109 @@ qcd_kernel(const double* __restrict__ mom, const double* __restrict__ w_in, int6
     }
 }
 
+// ------------------------------------------------ one event per wave
+//
+// Lanes carry helicity configurations (h = lane + 64 c); the event's
+// kinematics and wavefunction bases are wave-uniform, computed once per event
+// by qcd_setup_kernel and read through the scalar cache, so they occupy
+// neither vector registers nor LDS.  The helicity sum is a wave reduction.
+
+#ifndef MGRW_WAVE_WPE
+#define MGRW_WAVE_WPE 2
+#endif
+
+template <class Proc, typename T>
+struct event_data {
+    typename Proc::template kin<T> k;
+    typename Proc::template basis<T> b;
+};
+
+template <class Proc, typename T>
+__global__ void __launch_bounds__(kBlock)
+qcd_setup_kernel(const double* __restrict__ mom, int64_t n, double mt, event_data<Proc, T>* __restrict__ ev) {
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n) return;
+    double p[Proc::NEXT][4];
+    load_event<Proc::NEXT>(mom, n, e, p);
+    Proc::kinematics(p, mt, ev[e].k);
+    Proc::external_basis(p, mt, ev[e].b);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <class Proc, typename T>
+__global__ void __launch_bounds__(kBlock, MGRW_WAVE_WPE)
+qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* __restrict__ w_in, int64_t n,
+                qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
+    static_assert(Proc::NHEL % 64 == 0, "helicity configurations must fill whole waves");
+    const int64_t e = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (e >= n) return;   // whole wave; no barriers below
+    const int lane = threadIdx.x & 63;
+    const typename Proc::template kin<T>& k = ev[e].k;
+    const typename Proc::template basis<T>& b = ev[e].b;
+    const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
+    double me0 = 0.0;
+#pragma unroll 1
+    for (int kp = 0; kp < a.npts; ++kp) {
+        const qcd_point pt = a.pts[kp];
+        typename Proc::template coup<T> c = {T(pt.gs), T(pt.gs2), T(pt.gk)};
+        double acc = 0.0;
+#pragma unroll 1
+        for (int hc = 0; hc < Proc::NHEL; hc += 64) {
+            __asm__ volatile("" ::: "memory");
+            typename Proc::template ext<T> wf;
+            Proc::template external<T>(b, hc + lane, wf);
+            cx<T> J[Proc::K];
+            Proc::amplitude(wf, k, c, J);
+            acc += double(Proc::colour_sum(J));
+        }
+        const double me = wave_sum(acc) * Proc::NORM;
+        if (kp == 0) {
+            me0 = me;
+            if (lane == 0) {
+                if (a.mode == 1)
+                    out[e] = me;
+                else if (me0_out)
+                    me0_out[e] = me;
+            }
+        } else if (lane == 0) {
+            out[int64_t(kp - 1) * n + e] = reweighted(w, me, me0);
+        }
+    }
+}
+
 // Launch the reweight (mode 0) or single-point (mode 1) kernel of Proc at the
 // requested arithmetic; returns the launch status.
+template <class Proc, typename T>
+hipError_t launch_wave(const double* mom, const double* w_in, int64_t n, const qcd_launch& a, double* out,
+                       double* me0, hipStream_t s) {
+    if constexpr (Proc::NHEL % 64 != 0) {
+        return hipErrorInvalidConfiguration;
+    } else {
+        // per-event scratch for kinematics and bases (stream-ordered allocation)
+        event_data<Proc, T>* ev = nullptr;
+        hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(event_data<Proc, T>) * size_t(n), s);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL((qcd_setup_kernel<Proc, T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, mom, n, a.mt, ev);
+        hipLaunchKernelGGL((qcd_wave_kernel<Proc, T>), dim3(unsigned((n + kBlock / 64 - 1) / (kBlock / 64))),
+                           dim3(kBlock), 0, s, ev, w_in, n, a, out, me0);
+        err = hipGetLastError();
+        hipError_t ferr = hipFreeAsync(ev, s);
+        return err != hipSuccess ? err : ferr;
+    }
+}
+
 template <class Proc>
 hipError_t launch_qcd(int fp64, const double* mom, const double* w_in, int64_t n, const qcd_launch& a,
                       double* out, double* me0, hipStream_t s) {
+    if (a.mapping == MGRW_MAP_EVENT_PER_WAVE)
+        return fp64 ? launch_wave<Proc, double>(mom, w_in, n, a, out, me0, s)
+                    : launch_wave<Proc, float>(mom, w_in, n, a, out, me0, s);
     const unsigned blocks = unsigned((n + kBlock - 1) / kBlock);
     if (fp64)
         hipLaunchKernelGGL((qcd_kernel<Proc, double>), dim3(blocks), dim3(kBlock), 0, s, mom, w_in, n, a, out, me0);

@@ -75,6 +75,36 @@ def test_qcd_reweight_parity(torch_dev, name, n, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [1, 97, 261])
+def test_event_per_wave_mapping_parity(torch_dev, prec, n):
+    """The one-event-per-wave kernels (helicities on the lanes) against the
+    oracle, including a single event and a ragged count."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    mom, kap, w = qcd_case("gg_ttgg", n, seed_shift=500)
+    say(f"case event-per-wave gg_ttgg n={n} prec={prec}")
+    p = mg.Process("gg_ttgg", prec)
+    p.set_lane_mapping("event_per_wave")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    out = p.reweight(to_dev(torch, mom), w_in=to_dev(torch, w), me_base_out=me0)
+    me_b = p.eval_me(to_dev(torch, mom), 3)
+    torch.cuda.synchronize()
+    me_ref, w_ref = oracle_qcd("gg_ttgg", mom, kap, w)
+    assert relerr(me0.cpu().numpy(), me_ref[0]).max() <= TOL[prec]
+    assert relerr(out.cpu().numpy(), w_ref).max() <= TOL[prec]
+    assert relerr(me_b.cpu().numpy(), me_ref[4]).max() <= TOL[prec]
+
+
+def test_lane_mapping_option_errors(torch_dev):
+    import paper_2312_07440_amd as mg
+    from paper_2312_07440_amd import binding as bd
+    with pytest.raises(bd.MgrwError) as e:
+        mg.Process("gg_ttg", "mixed").set_lane_mapping("event_per_wave")   # 32 helicities
+    assert e.value.status == bd.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_qcd_eval_me_points(torch_dev, prec):
     import paper_2312_07440_amd as mg
     torch = torch_dev
