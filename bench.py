@@ -127,7 +127,7 @@ def main():
     import paper_2312_07440_amd as mg
     from synth import generate_events, kappa_points
 
-    ng = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4}[args.proc]
+    ng = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}[args.proc]
     log(f"generating {args.n} {args.proc} events")
     mom_np = generate_events(args.proc, args.n)
     kap = kappa_points(args.points)

@@ -39,24 +39,27 @@ def _run(cmd, verbose):
 
 
 def build(verbose=False, jobs=None):
-    from .gen import generate, QCD_PROCESSES
+    from .gen import generate, translation_units
     generate()
     os.makedirs(OBJ, exist_ok=True)
-    units = [os.path.join(CSRC, "mgrw_abi.hip"), os.path.join(CSRC, "mgrw_mlp.hip")] + [os.path.join(GEN, f"qcd_{p}.hip") for p in QCD_PROCESSES]
+    units = [os.path.join(CSRC, "mgrw_abi.hip"), os.path.join(CSRC, "mgrw_mlp.hip")] + \
+        [os.path.join(GEN, u) for u in translation_units()]
+    # the split program parts take longest: start them first
+    units.sort(key=lambda u: ("_part" not in u, u))
     objs = [os.path.join(OBJ, os.path.basename(u).replace(".hip", ".o")) for u in units]
-    jobs = jobs or min(len(units), os.cpu_count() or 4)
+    jobs = jobs or min(len(units) + 1, os.cpu_count() or 4)
+    host_tmp = HOSTLIB + ".tmp"
     with ThreadPoolExecutor(jobs) as ex:
         futs = [ex.submit(_run, [HIPCC, *HIP_FLAGS, "-c", u, "-o", o], verbose) for u, o in zip(units, objs)]
+        # host validation build (tests only), compiled alongside
+        futs.append(ex.submit(_run, ["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-I", CSRC, "-o", host_tmp,
+                                     os.path.join(CSRC, "host_check.cpp")], verbose))
         for f in futs:
             f.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
-    # host validation build (tests only)
-    tmp = HOSTLIB + ".tmp"
-    _run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I", CSRC, "-o", tmp,
-          os.path.join(CSRC, "host_check.cpp")], verbose)
-    os.replace(tmp, HOSTLIB)
+    os.replace(host_tmp, HOSTLIB)
     write_flops()
 
 

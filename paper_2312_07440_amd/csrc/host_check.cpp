@@ -13,6 +13,7 @@
 #include "gen/gg_tt.inc"
 #include "gen/gg_ttg.inc"
 #include "gen/gg_ttgg.inc"
+#include "gen/gg_ttggg.inc"
 
 namespace {
 
@@ -88,6 +89,7 @@ int mgrw_host_qcd_me(int ng, const double* mom, int64_t n, double mt, const doub
         case 2: me_events<mgrw::gg_tt, double>(mom, n, mt, pts, npts, me); return 0;
         case 3: me_events<mgrw::gg_ttg, double>(mom, n, mt, pts, npts, me); return 0;
         case 4: me_events<mgrw::gg_ttgg, double>(mom, n, mt, pts, npts, me); return 0;
+        case 5: me_events<mgrw::gg_ttggg, double>(mom, n, mt, pts, npts, me); return 0;
         default: return -2;
     }
 }
@@ -97,6 +99,7 @@ int mgrw_host_qcd_flops(int ng, long long* counts) {
         case 2: count_ops<mgrw::gg_tt>(counts); return 0;
         case 3: count_ops<mgrw::gg_ttg>(counts); return 0;
         case 4: count_ops<mgrw::gg_ttgg>(counts); return 0;
+        case 5: count_ops<mgrw::gg_ttggg>(counts); return 0;
         default: return -2;
     }
 }

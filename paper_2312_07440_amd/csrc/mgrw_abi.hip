@@ -20,6 +20,7 @@
 #include "gen/gg_tt.inc"
 #include "gen/gg_ttg.inc"
 #include "gen/gg_ttgg.inc"
+#include "gen/gg_ttggg.inc"
 
 using namespace mgrw;
 
@@ -32,6 +33,7 @@ using namespace mgrw;
 MGRW_DECLARE_LAUNCHER(gg_tt)
 MGRW_DECLARE_LAUNCHER(gg_ttg)
 MGRW_DECLARE_LAUNCHER(gg_ttgg)
+MGRW_DECLARE_LAUNCHER(gg_ttggg)
 
 namespace {
 
@@ -82,6 +84,8 @@ proc_info info_of(int proc) {
         case MGRW_GG_TTG: return {mgrw::gg_ttg::NEXT, mgrw::gg_ttg::K, mgrw::gg_ttg::NHEL, mgrw::gg_ttg::NDIAG};
         case MGRW_GG_TTGG:
             return {mgrw::gg_ttgg::NEXT, mgrw::gg_ttgg::K, mgrw::gg_ttgg::NHEL, mgrw::gg_ttgg::NDIAG};
+        case MGRW_GG_TTGGG:
+            return {mgrw::gg_ttggg::NEXT, mgrw::gg_ttggg::K, mgrw::gg_ttggg::NHEL, mgrw::gg_ttggg::NDIAG};
         default: return {0, 0, 0, 0};
     }
 }
@@ -174,6 +178,7 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
         case MGRW_GG_TT: return launched(launch_gg_tt(fp64, mom, w_in, n, a, out, me0, s));
         case MGRW_GG_TTG: return launched(launch_gg_ttg(fp64, mom, w_in, n, a, out, me0, s));
         case MGRW_GG_TTGG: return launched(launch_gg_ttgg(fp64, mom, w_in, n, a, out, me0, s));
+        case MGRW_GG_TTGGG: return launched(launch_gg_ttggg(fp64, mom, w_in, n, a, out, me0, s));
         default: return fail(MGRW_ERR_UNSUPPORTED, "process not built");
     }
 }
@@ -191,6 +196,8 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     if (info_of(proc).n_ext == 0) return fail(MGRW_ERR_UNSUPPORTED, "process not built into this library");
     if (proc == MGRW_EE_MUMU && prec != MGRW_FP64)
         return fail(MGRW_ERR_UNSUPPORTED, "e+e- -> mu+mu- is built in FP64 only");
+    if (proc == MGRW_GG_TTGGG && prec != MGRW_MIXED)
+        return fail(MGRW_ERR_UNSUPPORTED, "g g -> t tbar g g g is built in mixed precision only");
     mgrw_status st = check_params(proc, *base, "base");
     if (st != MGRW_OK) return st;
     mgrw_process* p = new (std::nothrow) mgrw_process;
@@ -257,6 +264,8 @@ mgrw_status mgrw_set_option(mgrw_process* p, int option, int64_t value) {
         return fail(MGRW_ERR_ARG, "unknown lane mapping");
     if (value == MGRW_MAP_EVENT_PER_WAVE && (p->proc == MGRW_EE_MUMU || info_of(p->proc).n_hel % 64 != 0))
         return fail(MGRW_ERR_UNSUPPORTED, "one event per wave needs a multiple of 64 helicity configurations");
+    if (value == MGRW_MAP_EVENT_PER_LANE && p->proc == MGRW_GG_TTGGG)
+        return fail(MGRW_ERR_UNSUPPORTED, "g g -> t tbar g g g runs one event per wave only");
     p->mapping = int(value);
     return MGRW_OK;
 }

@@ -180,6 +180,90 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* __rest
     }
 }
 
+// ------------------------------------------- programs split over kernels
+//
+// For the largest process the per-helicity program is split into NCHUNK
+// functions (consecutive closing groups); kernel C runs part C for every
+// point and helicity of a batch of events, one event per wave with the
+// helicity configurations on the lanes.  The colour-flow amplitudes J travel
+// between the parts through HBM in a [event][point][component][helicity]
+// layout (consecutive lanes touch consecutive words); the last part forms the
+// colour sum, the helicity sum (wave reduction) and the reweighted weights.
+
+template <class Proc, typename T, int C>
+__global__ void __launch_bounds__(kBlock, 1)
+qcd_part_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t nb, T* __restrict__ jbuf,
+                const double* __restrict__ w_in, int64_t n, qcd_launch a, double* __restrict__ out,
+                double* __restrict__ me0_out) {
+    constexpr int NH = Proc::NHEL, K2 = 2 * Proc::K;
+    constexpr bool LAST = C + 1 == Proc::NCHUNK;
+    static_assert(NH % 64 == 0, "helicity configurations must fill whole waves");
+    const int64_t el = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (el >= nb) return;   // whole wave; no barriers below
+    const int64_t e = e0 + el;
+    const int lane = threadIdx.x & 63;
+    const typename Proc::template kin<T>& k = ev[e].k;
+    const typename Proc::template basis<T>& b = ev[e].b;
+    const double w = (LAST && a.mode == 0 && w_in) ? w_in[e] : 1.0;
+    double me0 = 0.0;
+#pragma unroll 1
+    for (int kp = 0; kp < a.npts; ++kp) {
+        const qcd_point pt = a.pts[kp];
+        typename Proc::template coup<T> c = {T(pt.gs), T(pt.gs2), T(pt.gk)};
+        double acc = 0.0;
+#pragma unroll 1
+        for (int hc = 0; hc < NH; hc += 64) {
+            __asm__ volatile("" ::: "memory");
+            typename Proc::template ext<T> wf;
+            Proc::template external<T>(b, hc + lane, wf);
+            T* jp = jbuf + (el * a.npts + kp) * int64_t(K2) * NH + hc + lane;
+            cx<T> J[Proc::K];
+            if constexpr (C == 0) {
+#pragma unroll
+                for (int f = 0; f < Proc::K; ++f) J[f] = {T(0), T(0)};
+            } else {
+#pragma unroll
+                for (int f = 0; f < Proc::K; ++f) J[f] = {jp[(2 * f) * NH], jp[(2 * f + 1) * NH]};
+            }
+            Proc::template amplitude_part<C>(wf, k, c, J);
+            if constexpr (!LAST) {
+#pragma unroll
+                for (int f = 0; f < Proc::K; ++f) {
+                    jp[(2 * f) * NH] = J[f].re;
+                    jp[(2 * f + 1) * NH] = J[f].im;
+                }
+            } else {
+                acc += double(Proc::colour_sum(J));
+            }
+        }
+        if constexpr (LAST) {
+            const double me = wave_sum(acc) * Proc::NORM;
+            if (kp == 0) {
+                me0 = me;
+                if (lane == 0) {
+                    if (a.mode == 1)
+                        out[e] = me;
+                    else if (me0_out)
+                        me0_out[e] = me;
+                }
+            } else if (lane == 0) {
+                out[int64_t(kp - 1) * n + e] = reweighted(w, me, me0);
+            }
+        }
+    }
+}
+
+template <class Proc, typename T, int C>
+hipError_t launch_part(const event_data<Proc, T>* ev, int64_t e0, int64_t nb, T* jbuf, const double* w_in,
+                       int64_t n, const qcd_launch& a, double* out, double* me0, hipStream_t s) {
+    hipLaunchKernelGGL((qcd_part_kernel<Proc, T, C>), dim3(unsigned((nb + kBlock / 64 - 1) / (kBlock / 64))),
+                       dim3(kBlock), 0, s, ev, e0, nb, jbuf, w_in, n, a, out, me0);
+    return hipGetLastError();
+}
+
+// Events per batch of the split programs (bounds the HBM buffer for J).
+constexpr int64_t kPartBatch = 8192;
+
 // Launch the reweight (mode 0) or single-point (mode 1) kernel of Proc at the
 // requested arithmetic; returns the launch status.
 template <class Proc, typename T>

@@ -446,7 +446,16 @@ class Emitter:
         self.n_amp += 1
         self.accumulate(a, seq)
 
-    def program(self):
+    def group_keys(self):
+        """Closing groups in program order: 'leaf', then gluon-set masks."""
+        keys = set()
+        for seq in diagrams(self.ng):
+            kind, U, j = closing(seq)
+            keys.add("leaf" if kind == "leaf" else U)
+        return ["leaf"] * ("leaf" in keys) + sorted((k for k in keys if k != "leaf"), key=lambda m: (popcount(m), m))
+
+    def program(self, only=None):
+        """Emit the program; `only` restricts it to a set of group keys."""
         diags = diagrams(self.ng)
         groups = {}
         leaf = []
@@ -459,11 +468,14 @@ class Emitter:
         # single-gluon row/column currents and the t tbar current are shared
         # leaf-only diagrams: iterate over the column side first
         leaf.sort(key=lambda x: ([t.key for t in x[0][x[1] + 1:]], [t.key for t in x[0]]))
-        self.emit("// leaf-only diagrams")
-        for seq, j in leaf:
-            self.close_ttg(seq, j)
+        if only is None or "leaf" in only:
+            self.emit("// leaf-only diagrams")
+            for seq, j in leaf:
+                self.close_ttg(seq, j)
         self.cache = {}
         for U in sorted(groups, key=lambda m: (popcount(m), m)):
+            if only is not None and U not in only:
+                continue
             items = groups[U]
             order = {t.key: i for i, t in enumerate(trees(U))}
 
@@ -487,11 +499,49 @@ class Emitter:
         return self.lines
 
 
-def emit_process(name, ng):
-    """C++ source of the process struct for g g -> t tbar + (ng-2) g."""
+def split_groups(ng, chunks):
+    """Consecutive closing groups partitioned into `chunks` parts of similar
+    program size; each part is emitted as its own function (and kernel)."""
+    keys = Emitter(ng).group_keys()
+    sizes = [len(Emitter(ng).program({k})) for k in keys]
+    total, parts, cur, acc = sum(sizes), [], [], 0
+    for k, sz in zip(keys, sizes):
+        cur.append(k)
+        acc += sz
+        if acc >= total * (len(parts) + 1) / chunks and len(parts) < chunks - 1:
+            parts.append(cur)
+            cur = []
+    parts.append(cur)
+    return [p for p in parts if p]
+
+
+def emit_process(name, ng, chunks=1):
+    """C++ source of the process struct for g g -> t tbar + (ng-2) g.
+
+    With chunks > 1 the per-helicity program is split into that many
+    functions amplitude_part<C> over consecutive closing groups, each adding
+    its diagrams to J; amplitude() zeroes J and runs all parts."""
     from math import factorial, gcd
     em = Emitter(ng)
-    body = em.program()
+    if chunks > 1:
+        parts = split_groups(ng, chunks)
+        part_ems = []
+        for p in parts:
+            e = Emitter(ng)
+            e.program(set(p))
+            part_ems.append(e)
+        for e in part_ems:
+            em.P_needed |= e.P_needed
+            em.iP_needed |= e.iP_needed
+            em.qL_needed |= e.qL_needed
+            em.qR_needed |= e.qR_needed
+            em.n_amp += e.n_amp
+            em.n_jterms += e.n_jterms
+            for kk, v in e.counts.items():
+                em.counts[kk] += v
+        body = None
+    else:
+        body = em.program()
     K = len(em.flows)
     next_ = ng + 2
     cf = colour_matrix_loops(ng)
@@ -591,12 +641,35 @@ def emit_process(name, ng):
     w("  template <typename T> struct coup { T g, g2, gk; };")
     w("  // Colour-flow amplitudes J of one helicity (common phase dropped).")
     w("  // k: the event's kin<T> (in registers or in LDS).")
-    w("  template <typename T, typename KN>")
-    w("  static MGRW_HD void amplitude(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {")
-    w("    for (int i = 0; i < K; ++i) J[i] = {T(0), T(0)};")
-    for line in body:
-        w("    " + line)
-    w("  }")
+    if body is not None:
+        w("  static constexpr int NCHUNK = 1;")
+        w("  template <typename T, typename KN>")
+        w("  static MGRW_HD void amplitude(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {")
+        w("    for (int i = 0; i < K; ++i) J[i] = {T(0), T(0)};")
+        for line in body:
+            w("    " + line)
+        w("  }")
+    else:
+        w(f"  static constexpr int NCHUNK = {len(part_ems)};")
+        for ci, e in enumerate(part_ems):
+            w(f"  // part {ci}: closing groups " + ", ".join(
+                "leaf" if g == "leaf" else str(bits(g)) for g in parts[ci]))
+            w("  template <typename T, typename KN>")
+            w(f"  static MGRW_HD void amplitude_part{ci}(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {{")
+            for line in e.lines:
+                w("    " + line)
+            w("  }")
+        w("  template <int C, typename T, typename KN>")
+        w("  static MGRW_HD void amplitude_part(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {")
+        for ci in range(len(part_ems)):
+            w(f"    {'if' if ci == 0 else 'else if'} constexpr (C == {ci}) amplitude_part{ci}<T>(w, k, c, J);")
+        w("  }")
+        w("  template <typename T, typename KN>")
+        w("  static MGRW_HD void amplitude(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {")
+        w("    for (int i = 0; i < K; ++i) J[i] = {T(0), T(0)};")
+        for ci in range(len(part_ems)):
+            w(f"    amplitude_part{ci}<T>(w, k, c, J);")
+        w("  }")
     w("  template <typename T>")
     w("  static MGRW_HD T colour_sum(const cx<T>* J) {")
     w("    T s = T(0);")

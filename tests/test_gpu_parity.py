@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 ALS, MT = 0.118, 173.0
 EW = dict(alpha=1 / 132.5, sw2=0.2312, mz=91.1876, wz=2.4952)
-NG = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4}
+NG = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 TOL = {"fp64": 1e-12, "mixed": 1e-5}
 
 
@@ -250,3 +250,81 @@ def test_full_size_sampled_parity(torch_dev):
     say(f"  sampled W' rel err max {e.max():.3e} median {np.median(e):.3e}")
     assert relerr(me0[torch.from_numpy(idx).to("cuda:0")].cpu().numpy(), me_ref[0]).max() <= 1e-5
     assert e.max() <= 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 70])
+def test_gg_ttggg_parity(torch_dev, n):
+    """g g -> t tbar g g g (1240 diagrams, 120 flows, program split over
+    kernels), mixed precision, against the oracle."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    mom, kap, w = qcd_case("gg_ttggg", n, seed_shift=300)
+    kap = kap[::4]
+    say(f"case gg_ttggg n={n}")
+    p = mg.Process("gg_ttggg", "mixed")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    out = p.reweight(to_dev(torch, mom), w_in=to_dev(torch, w), me_base_out=me0)
+    torch.cuda.synchronize()
+    me_ref, w_ref = oracle_qcd("gg_ttggg", mom, kap, w)
+    e_me, e_w = relerr(me0.cpu().numpy(), me_ref[0]), relerr(out.cpu().numpy(), w_ref)
+    say(f"  |M|^2 rel err max {e_me.max():.3e}; W' rel err max {e_w.max():.3e} median {np.median(e_w):.3e}")
+    assert e_me.max() <= TOL["mixed"]
+    assert e_w.max() <= TOL["mixed"]
+
+
+def test_gg_ttggg_batch_boundary(torch_dev):
+    """More events than one internal batch (8192): events on both sides of
+    the boundary and at the ends, against the oracle."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 8192 + 37
+    mom, kap, _ = qcd_case("gg_ttggg", n, seed_shift=7000)
+    kap = kap[::8]
+    say(f"case gg_ttggg batch boundary n={n}")
+    p = mg.Process("gg_ttggg", "mixed")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    out = p.reweight(to_dev(torch, mom))
+    torch.cuda.synchronize()
+    idx = np.array([0, 1, 4000, 8190, 8191, 8192, 8193, n - 2, n - 1])
+    sub = np.ascontiguousarray(mom[:, :, idx])
+    _, w_ref = oracle_qcd("gg_ttggg", sub, kap, np.ones(len(idx)))
+    assert relerr(out.cpu().numpy()[:, idx], w_ref).max() <= TOL["mixed"]
+
+
+def test_gg_ttggg_full_configuration_uneven_batches(torch_dev):
+    """The full g g -> t tbar g g g workload: 2^20 events handed over in
+    seeded uneven batches of 65 536..262 144 events (the last one the
+    remainder), 16 points; sampled events against the oracle."""
+    import paper_2312_07440_amd as mg
+    from synth.rng import uniform
+    from synth.phase_space import PROCESSES, STREAM_BATCH
+    torch = torch_dev
+    spec = PROCESSES["gg_ttggg"]
+    n = spec.n_events
+    say(f"case gg_ttggg full configuration n={n}: generating events")
+    mom = generate_events("gg_ttggg", n)
+    kap = kappa_points(16)
+    p = mg.Process("gg_ttggg", "mixed")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    sizes, b = [], 0
+    while sum(sizes) < n:
+        s = int(65536 + uniform(spec.seed, STREAM_BATCH, b, 0) * (262144 - 65536 + 1))
+        sizes.append(min(s, n - sum(sizes)))
+        b += 1
+    out = np.empty((16, n))
+    e0 = 0
+    for s in sizes:
+        say(f"  batch [{e0}, {e0 + s})")
+        o = p.reweight(to_dev(torch, mom[:, :, e0:e0 + s]))
+        torch.cuda.synchronize()
+        out[:, e0:e0 + s] = o.cpu().numpy()
+        e0 += s
+    idx = np.sort(np.random.default_rng(4).choice(n, 24, replace=False))
+    idx = np.unique(np.concatenate([idx, [0, n - 1], np.cumsum(sizes)[:-1], np.cumsum(sizes)[:-1] - 1]))
+    sub = np.ascontiguousarray(mom[:, :, idx])
+    say(f"  oracle on {len(idx)} sampled events")
+    _, w_ref = oracle_qcd("gg_ttggg", sub, kap, np.ones(len(idx)))
+    e = relerr(out[:, idx], w_ref)
+    say(f"  batches {sizes}; sampled W' rel err max {e.max():.3e} median {np.median(e):.3e}")
+    assert e.max() <= TOL["mixed"]
