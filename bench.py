@@ -100,6 +100,33 @@ def surrogate_leg(args, proc, mom, exact_out, kap, torch, generate_events):
             "timing": "host wall clock per call (the call synchronises once for the audit statistics)"}
 
 
+def kpoly_leg(args, proc, mom, exact_out, stream, torch):
+    """The kappa-polynomial exact variant on the same batch and points: timed
+    with device events like the main leg, checked against its weights."""
+    kout = torch.empty_like(exact_out)
+    for _ in range(args.warmup):
+        proc.reweight_kpoly(mom, out=kout)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    for i in range(args.steps):
+        starts[i].record(stream)
+        proc.reweight_kpoly(mom, out=kout)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    f = json.load(open(os.path.join(HERE, "paper_2312_07440_amd", "csrc", "gen", "flops.json")))[args.proc]
+    fpe = proc.n_hel * f["kpoly_per_helicity_flops"]
+    achieved = fpe * args.n / (ms * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
+    diff = float(torch.abs(kout / exact_out - 1.0).max())
+    return {"value": args.n * args.points / (ms * 1e-3), "unit": "events*points/s", "ms_per_step": ms,
+            "path": "exact, kappa polynomial (one unit-coupling program per helicity for all points)",
+            "max_rel_diff_vs_exact": diff,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved / peak, "flops_per_event": fpe}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +139,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-kpoly", action="store_true")
     ap.add_argument("--train-events", type=int, default=1 << 21)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--audit", type=float, default=0.01)
@@ -191,6 +219,9 @@ def main():
                      "frac": achieved / peak, "traffic": traffic,
                      "flops_per_event": fpe, "per_helicity_flops": fcounts["per_helicity_flops"]},
     }
+    if not args.no_kpoly and args.proc in ("gg_tt", "gg_ttg", "gg_ttgg"):
+        log("kappa-polynomial variant")
+        res["kpoly"] = kpoly_leg(args, proc, mom, out, stream, torch)
     if not args.no_surrogate:
         res["surrogate"] = surrogate_leg(args, proc, mom, out, kap, torch, generate_events)
     if not args.no_cpu_baseline:

@@ -120,6 +120,18 @@ mgrw_status mgrw_eval_me(mgrw_process *p, const double *mom, int64_t n_events, i
 mgrw_status mgrw_reweight(mgrw_process *p, const double *mom, const double *w_in, int64_t n_events,
                           double *w_out, double *me_base_out, void *stream);
 
+/* Exact reweighting by the kappa polynomial.  Same contract and results (to
+ * rounding) as mgrw_reweight, by a different evaluation: every diagram carries
+ * g_s^n kappa^k with k its number of top-gluon vertices, so one evaluation per
+ * helicity at unit couplings gives the amplitudes J_k of each power and
+ *   |M|^2(g_s, kappa) = g_s^(2n) sum_{k,k'} kappa^(k+k') Re(J_k^+ CF J_k')
+ * for every point at the cost of a few colour products: the work no longer
+ * grows with the number of points.  Points may differ from the base in
+ * alphas and kappa_ttg.  g g -> t tbar + 0..2 g.  Errors: as mgrw_reweight;
+ * MGRW_ERR_UNSUPPORTED for other processes. */
+mgrw_status mgrw_reweight_kpoly(mgrw_process *p, const double *mom, const double *w_in, int64_t n_events,
+                                double *w_out, double *me_base_out, void *stream);
+
 /* Static properties of the process: external particles, colour flows,
  * helicity configurations evaluated per event and point, Feynman diagrams.
  * Any output pointer may be NULL.  Errors: MGRW_ERR_ARG (null handle). */

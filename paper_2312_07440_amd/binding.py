@@ -96,6 +96,8 @@ def lib():
     L.mgrw_surrogate_set.restype = ctypes.c_int
     L.mgrw_surrogate_fwd_bwd.argtypes = [vp, vp, vp, vp, i64, vp, fp, ctypes.POINTER(ctypes.c_double), vp]
     L.mgrw_surrogate_fwd_bwd.restype = ctypes.c_int
+    L.mgrw_reweight_kpoly.argtypes = [vp, dp, dp, i64, dp, dp, vp]
+    L.mgrw_reweight_kpoly.restype = ctypes.c_int
     L.mgrw_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
     L.mgrw_set_option.restype = ctypes.c_int
     _lib = L
@@ -199,6 +201,17 @@ class Process:
         check(lib().mgrw_reweight(self._h, _ptr(mom, "mom"), _ptr(w_in, "w_in", n, allow_none=True), n,
                                   _ptr(out, "out", self.n_points * n),
                                   _ptr(me_base_out, "me_base_out", n, allow_none=True), _stream(stream)))
+        return out
+
+    def reweight_kpoly(self, mom, w_in=None, out=None, me_base_out=None, stream=None):
+        """Exact reweighting through the kappa polynomial (mgrw_reweight_kpoly)."""
+        import torch
+        n = self._n(mom)
+        if out is None:
+            out = torch.empty((self.n_points, n), dtype=torch.float64, device=mom.device)
+        check(lib().mgrw_reweight_kpoly(self._h, _ptr(mom, "mom"), _ptr(w_in, "w_in", n, allow_none=True), n,
+                                        _ptr(out, "out", self.n_points * n),
+                                        _ptr(me_base_out, "me_base_out", n, allow_none=True), _stream(stream)))
         return out
 
     # ---------------------------------------------------------- surrogate

@@ -74,6 +74,10 @@ def write_flops():
         out[name] = {"per_helicity_add": c[0], "per_helicity_mul": c[1],
                      "per_helicity_flops": c[0] + c[1],
                      "colour_sum_flops": c[2] + c[3], "external_flops": c[4] + c[5]}
+        lib.mgrw_host_kpoly_flops.restype = ctypes.c_longlong
+        kf = lib.mgrw_host_kpoly_flops(ng)
+        if kf > 0:
+            out[name]["kpoly_per_helicity_flops"] = kf
     with open(os.path.join(GEN, "flops.json"), "w") as f:
         json.dump(out, f, indent=1)
     return out

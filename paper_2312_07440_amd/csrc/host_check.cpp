@@ -45,6 +45,36 @@ void me_events(const double* mom, int64_t n, double mt, const mgrw::qcd_point* p
     }
 }
 
+template <class Proc, typename T>
+void me_events_kpoly(const double* mom, int64_t n, double mt, const mgrw::qcd_point* pts, int npts, double* me) {
+    for (int64_t e = 0; e < n; ++e) {
+        double p[Proc::NEXT][4];
+        for (int i = 0; i < Proc::NEXT; ++i)
+            for (int m = 0; m < 4; ++m) p[i][m] = mom[(int64_t(i) * 4 + m) * n + e];
+        mgrw::qcd_event<Proc, T> ev;
+        ev.setup(p, mt);
+        double B[mgrw::kpoly_pairs<Proc>()] = {};
+        for (int h = 0; h < Proc::NHEL; ++h) mgrw::kpoly_helicity<Proc, T>(ev.k, ev.b, h, B);
+        for (int k = 0; k < npts; ++k) me[int64_t(k) * n + e] = mgrw::kpoly_me<Proc>(B, pts[k].gs, pts[k].gk / pts[k].gs);
+    }
+}
+
+// add + mul of one helicity of the kappa-polynomial evaluation
+template <class Proc>
+long long count_kpoly() {
+    double p[Proc::NEXT][4];
+    for (int i = 0; i < Proc::NEXT; ++i)
+        for (int m = 0; m < 4; ++m) p[i][m] = 1.0 + i + 0.25 * m;
+    typename Proc::template kin<cfloat> k;
+    Proc::kinematics(p, 173.0, k);
+    typename Proc::template basis<cfloat> b;
+    Proc::external_basis(p, 173.0, b);
+    double B[mgrw::kpoly_pairs<Proc>()] = {};
+    cfloat::n_add = cfloat::n_mul = 0;
+    mgrw::kpoly_helicity<Proc, cfloat>(k, b, 5, B);
+    return cfloat::n_add + cfloat::n_mul;
+}
+
 // counts[0..1]: add, mul of one helicity program (external wavefunctions,
 // diagram chains and colour sum); counts[2..3]: the colour sum alone;
 // counts[4..5]: external wavefunctions alone.
@@ -91,6 +121,31 @@ int mgrw_host_qcd_me(int ng, const double* mom, int64_t n, double mt, const doub
         case 4: me_events<mgrw::gg_ttgg, double>(mom, n, mt, pts, npts, me); return 0;
         case 5: me_events<mgrw::gg_ttggg, double>(mom, n, mt, pts, npts, me); return 0;
         default: return -2;
+    }
+}
+
+int mgrw_host_qcd_me_kpoly(int ng, const double* mom, int64_t n, double mt, const double* pts_gs_gk, int npts,
+                           double* me) {
+    if (npts < 1 || npts > 64 || n < 0) return -1;
+    mgrw::qcd_point pts[64];
+    for (int k = 0; k < npts; ++k) {
+        double gs = pts_gs_gk[2 * k], kap = pts_gs_gk[2 * k + 1];
+        pts[k] = {gs, gs * gs, gs * kap};
+    }
+    switch (ng) {
+        case 2: me_events_kpoly<mgrw::gg_tt, double>(mom, n, mt, pts, npts, me); return 0;
+        case 3: me_events_kpoly<mgrw::gg_ttg, double>(mom, n, mt, pts, npts, me); return 0;
+        case 4: me_events_kpoly<mgrw::gg_ttgg, double>(mom, n, mt, pts, npts, me); return 0;
+        default: return -2;
+    }
+}
+
+long long mgrw_host_kpoly_flops(int ng) {
+    switch (ng) {
+        case 2: return count_kpoly<mgrw::gg_tt>();
+        case 3: return count_kpoly<mgrw::gg_ttg>();
+        case 4: return count_kpoly<mgrw::gg_ttgg>();
+        default: return -1;
     }
 }
 

@@ -138,7 +138,7 @@ mgrw_status launched(hipError_t err) {
 
 // Shared body of eval_me (mode 1, one point) and reweight (mode 0).
 mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t n, const mgrw_params* pts,
-                int npts, int mode, double* out, double* me0, void* stream) {
+                int npts, int mode, double* out, double* me0, void* stream, int kpoly = 0) {
     if (n < 0) return fail(MGRW_ERR_ARG, "n_events < 0");
     if (n == 0) return MGRW_OK;
     mgrw_status st;
@@ -173,6 +173,7 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
     // whole waves (kinematics then live in the scalar cache, not in VGPRs/LDS)
     a.mapping = p->mapping != MGRW_MAP_AUTO ? p->mapping
                 : (info_of(p->proc).n_hel % 64 == 0 ? MGRW_MAP_EVENT_PER_WAVE : MGRW_MAP_EVENT_PER_LANE);
+    a.kpoly = kpoly;
     const int fp64 = p->prec == MGRW_FP64;
     switch (p->proc) {
         case MGRW_GG_TT: return launched(launch_gg_tt(fp64, mom, w_in, n, a, out, me0, s));
@@ -245,6 +246,18 @@ mgrw_status mgrw_reweight(mgrw_process* p, const double* mom, const double* w_in
     all[0] = p->base;
     for (int k = 0; k < p->n_points; ++k) all[k + 1] = p->points[k];
     return run(p, mom, w_in, n_events, all, p->n_points + 1, 0, w_out, me_base_out, stream);
+}
+
+mgrw_status mgrw_reweight_kpoly(mgrw_process* p, const double* mom, const double* w_in, int64_t n_events,
+                                double* w_out, double* me_base_out, void* stream) {
+    if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
+    if (p->proc == MGRW_EE_MUMU || p->proc == MGRW_GG_TTGGG)
+        return fail(MGRW_ERR_UNSUPPORTED, "kappa-polynomial reweighting: g g -> t tbar + 0..2 g only");
+    if (p->n_points == 0) return fail(MGRW_ERR_STATE, "no parameter points set");
+    mgrw_params all[kMaxLaunchPoints];
+    all[0] = p->base;
+    for (int k = 0; k < p->n_points; ++k) all[k + 1] = p->points[k];
+    return run(p, mom, w_in, n_events, all, p->n_points + 1, 0, w_out, me_base_out, stream, 1);
 }
 
 mgrw_status mgrw_process_info(const mgrw_process* p, int* n_ext, int* n_flows, int* n_hel, int* n_diagrams) {

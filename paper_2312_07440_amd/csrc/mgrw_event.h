@@ -47,6 +47,66 @@ MGRW_HD double point_me(const KN& k, const BS& b, const qcd_point& pt) {
     return acc * Proc::NORM;
 }
 
+// ------------------------------------------------ kappa-polynomial form
+//
+// Every diagram of g g -> t tbar + n g carries g^NG kappa^k, k its number of
+// top-gluon vertices, so J(g, kappa) = g^NG sum_k kappa^k J_k with J_k from one
+// evaluation at unit couplings, and
+//   |M|^2(g, kappa) = NORM g^(2 NG) sum_{a<=b} (2 - delta_ab) kappa^(a+b+2) B_ab,
+//   B_ab = sum_h Re(J_a^+ CF J_b)            (a, b = 0..NG-1 for powers 1..NG).
+// Exact: the same diagrams as the plain program, evaluated once for any
+// number of parameter points.
+
+template <typename T>
+struct kpoly_acc { using type = T; };
+template <>
+struct kpoly_acc<float> { using type = double; };
+
+template <class Proc>
+constexpr int kpoly_pairs() {
+    return Proc::NG * (Proc::NG + 1) / 2;
+}
+
+// Add one helicity configuration's B_ab (pair (a <= b) at b(b+1)/2 + a).
+template <class Proc, typename T, typename KN, typename BS>
+MGRW_HD void kpoly_helicity(const KN& k, const BS& b, int h, double* B) {
+    typename Proc::template coup<T> c = {T(1), T(1), T(1)};
+    typename Proc::template ext<T> w;
+    Proc::template external<T>(b, h, w);
+    cx<T> J[Proc::NG * Proc::K];
+    Proc::amplitude_kpoly(w, k, c, J);
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+#endif
+    for (int pb = 0; pb < Proc::NG; ++pb) {
+        // The terms of different kappa powers cancel strongly against each
+        // other (no single power is gauge invariant), so the colour products
+        // of float amplitudes are accumulated in double.
+        using TA = typename kpoly_acc<T>::type;
+        cx<TA> Z[Proc::K];
+        Proc::template colour_matvec<TA, T>(J + pb * Proc::K, Z);
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+#endif
+        for (int pa = 0; pa <= pb; ++pa)
+            B[pb * (pb + 1) / 2 + pa] += double(Proc::template re_dot<TA, T>(J + pa * Proc::K, Z));
+    }
+}
+
+// |M|^2 at couplings (gs, kappa) from the helicity-summed B.
+template <class Proc>
+MGRW_HD double kpoly_me(const double* B, double gs, double kappa) {
+    double kp[2 * Proc::NG + 1];
+    kp[0] = 1.0;
+    for (int i = 1; i <= 2 * Proc::NG; ++i) kp[i] = kp[i - 1] * kappa;
+    double s = 0.0;
+    for (int pb = 0; pb < Proc::NG; ++pb)
+        for (int pa = 0; pa <= pb; ++pa) s += (pa == pb ? 1.0 : 2.0) * kp[pa + pb + 2] * B[pb * (pb + 1) / 2 + pa];
+    double g2n = 1.0;
+    for (int i = 0; i < Proc::NG; ++i) g2n *= gs * gs;
+    return s * g2n * Proc::NORM;
+}
+
 // Helicity-independent state of one event held by value (host build, and the
 // FP64 kernels): kinematics with double-precision propagator denominators,
 // and the external-wavefunction bases.

@@ -22,6 +22,7 @@ struct qcd_launch {
     int mode;        // 0: reweight, 1: |M|^2 of pts[0] only
     double mt;
     int mapping;     // MGRW_MAP_EVENT_PER_LANE or MGRW_MAP_EVENT_PER_WAVE
+    int kpoly;       // 1: kappa-polynomial evaluation (one program per helicity for all points)
 };
 
 struct ew_launch {
@@ -180,6 +181,86 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* __rest
     }
 }
 
+// ------------------------------------------------ kappa-polynomial kernels
+
+// Outputs of one event from its helicity-summed B.
+template <class Proc>
+__device__ __forceinline__ void kpoly_outputs(const double* B, const qcd_launch& a, int64_t n, int64_t e,
+                                              double w, double* __restrict__ out, double* __restrict__ me0_out) {
+    double me0 = 0.0;
+    for (int kp = 0; kp < a.npts; ++kp) {
+        const double me = kpoly_me<Proc>(B, a.pts[kp].gs, a.pts[kp].gk / a.pts[kp].gs);
+        if (kp == 0) {
+            me0 = me;
+            if (a.mode == 1)
+                out[e] = me;
+            else if (me0_out)
+                me0_out[e] = me;
+        } else {
+            out[int64_t(kp - 1) * n + e] = reweighted(w, me, me0);
+        }
+    }
+}
+
+// One event per lane (processes with fewer than 64 helicity configurations).
+template <class Proc, typename T>
+__global__ void __launch_bounds__(kBlock)
+qcd_kpoly_lane_kernel(const double* __restrict__ mom, const double* __restrict__ w_in, int64_t n, qcd_launch a,
+                      double* __restrict__ out, double* __restrict__ me0_out) {
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n) return;
+    double p[Proc::NEXT][4];
+    load_event<Proc::NEXT>(mom, n, e, p);
+    typename Proc::template kin<T> k;
+    typename Proc::template basis<T> b;
+    Proc::kinematics(p, a.mt, k);
+    Proc::external_basis(p, a.mt, b);
+    double B[kpoly_pairs<Proc>()] = {};
+#pragma unroll 1
+    for (int h = 0; h < Proc::NHEL; ++h) kpoly_helicity<Proc, T>(k, b, h, B);
+    kpoly_outputs<Proc>(B, a, n, e, (a.mode == 0 && w_in) ? w_in[e] : 1.0, out, me0_out);
+}
+
+// One event per wave, helicity configurations on the lanes.
+template <class Proc, typename T>
+__global__ void __launch_bounds__(kBlock)
+qcd_kpoly_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* __restrict__ w_in, int64_t n,
+                      qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
+    const int64_t e = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (e >= n) return;
+    const int lane = threadIdx.x & 63;
+    double B[kpoly_pairs<Proc>()] = {};
+#pragma unroll 1
+    for (int hc = 0; hc < Proc::NHEL; hc += 64) {
+        __asm__ volatile("" ::: "memory");
+        kpoly_helicity<Proc, T>(ev[e].k, ev[e].b, hc + lane, B);
+    }
+#pragma unroll
+    for (int i = 0; i < kpoly_pairs<Proc>(); ++i) B[i] = wave_sum(B[i]);
+    if (lane == 0) kpoly_outputs<Proc>(B, a, n, e, (a.mode == 0 && w_in) ? w_in[e] : 1.0, out, me0_out);
+}
+
+template <class Proc, typename T>
+hipError_t launch_kpoly(const double* mom, const double* w_in, int64_t n, const qcd_launch& a, double* out,
+                        double* me0, hipStream_t s) {
+    if constexpr (Proc::NHEL % 64 == 0) {
+        event_data<Proc, T>* ev = nullptr;
+        hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(event_data<Proc, T>) * size_t(n), s);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL((qcd_setup_kernel<Proc, T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, mom, n, a.mt, ev);
+        hipLaunchKernelGGL((qcd_kpoly_wave_kernel<Proc, T>), dim3(unsigned((n + kBlock / 64 - 1) / (kBlock / 64))),
+                           dim3(kBlock), 0, s, ev, w_in, n, a, out, me0);
+        err = hipGetLastError();
+        hipError_t ferr = hipFreeAsync(ev, s);
+        return err != hipSuccess ? err : ferr;
+    } else {
+        hipLaunchKernelGGL((qcd_kpoly_lane_kernel<Proc, T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, s, mom, w_in, n, a, out, me0);
+        return hipGetLastError();
+    }
+}
+
 // ------------------------------------------- programs split over kernels
 //
 // For the largest process the per-helicity program is split into NCHUNK
@@ -289,6 +370,9 @@ hipError_t launch_wave(const double* mom, const double* w_in, int64_t n, const q
 template <class Proc>
 hipError_t launch_qcd(int fp64, const double* mom, const double* w_in, int64_t n, const qcd_launch& a,
                       double* out, double* me0, hipStream_t s) {
+    if (a.kpoly)
+        return fp64 ? launch_kpoly<Proc, double>(mom, w_in, n, a, out, me0, s)
+                    : launch_kpoly<Proc, float>(mom, w_in, n, a, out, me0, s);
     if (a.mapping == MGRW_MAP_EVENT_PER_WAVE)
         return fp64 ? launch_wave<Proc, double>(mom, w_in, n, a, out, me0, s)
                     : launch_wave<Proc, float>(mom, w_in, n, a, out, me0, s);

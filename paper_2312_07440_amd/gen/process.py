@@ -285,8 +285,9 @@ class Emitter:
     external wavefunctions, the t tbar current and the single-gluon row and
     column currents are shared by all groups."""
 
-    def __init__(self, ng, global_leaf_lr=True):
+    def __init__(self, ng, global_leaf_lr=True, kpoly=False):
         self.ng = ng
+        self.kpoly = kpoly          # accumulate J per power of kappa (J[(k-1)*K + w])
         self.full = (1 << ng) - 1
         self.lines = []
         self.nvar = 0
@@ -406,6 +407,8 @@ class Emitter:
         for w, c in sorted(col.items(), key=lambda x: self.flow_index[x[0]]):
             assert c in (1, -1), (seq, w, c)
             j = self.flow_index[w]
+            if self.kpoly:   # one top-gluon vertex per attached tree: kappa^len(seq)
+                j += (len(seq) - 1) * len(self.flows)
             op = "+" if c > 0 else "-"
             self.emit(f"J[{j}] = J[{j}] {op} {amp};")
             self.n_jterms += 1
@@ -669,6 +672,33 @@ def emit_process(name, ng, chunks=1):
         w("    for (int i = 0; i < K; ++i) J[i] = {T(0), T(0)};")
         for ci in range(len(part_ems)):
             w(f"    amplitude_part{ci}<T>(w, k, c, J);")
+        w("  }")
+    if body is not None:
+        # kappa-polynomial form of the same diagrams: J split by power of kappa
+        ek = Emitter(ng, kpoly=True)
+        kbody = ek.program()
+        w("  // Same diagrams at unit couplings, J[(k-1)*K + w] collecting the diagrams")
+        w("  // with k top-gluon vertices: J(g, kappa) = g^NG sum_k kappa^k J_k.")
+        w("  template <typename T, typename KN>")
+        w("  static MGRW_HD void amplitude_kpoly(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {")
+        w("    for (int i = 0; i < NG * K; ++i) J[i] = {T(0), T(0)};")
+        for line in kbody:
+            w("    " + line)
+        w("  }")
+        w("  // Z = CF J (integer numerators), accumulated in T from inputs of type TI.")
+        w("  template <typename T, typename TI>")
+        w("  static MGRW_HD void colour_matvec(const cx<TI>* J, cx<T>* Z) {")
+        for i in range(K):
+            terms = [(num[i][j], j) for j in range(K) if num[i][j]]
+            re = " + ".join(f"T({c}) * T(J[{j}].re)" for c, j in terms)
+            im = " + ".join(f"T({c}) * T(J[{j}].im)" for c, j in terms)
+            w(f"    Z[{i}] = {{{re}, {im}}};")
+        w("  }")
+        w("  template <typename T, typename TI>")
+        w("  static MGRW_HD T re_dot(const cx<TI>* A, const cx<T>* Z) {")
+        w("    T s = T(0);")
+        w("    for (int i = 0; i < K; ++i) s = (s + T(A[i].re) * Z[i].re) + T(A[i].im) * Z[i].im;")
+        w("    return s;")
         w("  }")
     w("  template <typename T>")
     w("  static MGRW_HD T colour_sum(const cx<T>* J) {")

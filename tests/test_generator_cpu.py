@@ -88,3 +88,47 @@ def test_flop_counts_recorded():
     # symmetric colour sum of K flows: row i costs 2(1 + 2(K-1-i)) + 4 flops -> 2K^2 + 4K
     for name, K in (("gg_tt", 2), ("gg_ttg", 6), ("gg_ttgg", 24)):
         assert f[name]["colour_sum_flops"] == 2 * K * K + 4 * K
+
+
+@pytest.mark.parametrize("name,ng,n", [("gg_tt", 2, 64), ("gg_ttg", 3, 32), ("gg_ttgg", 4, 6)])
+def test_host_kappa_polynomial_matches_oracle(name, ng, n):
+    """The kappa-polynomial evaluation (amplitudes split by the number of
+    top-gluon vertices, one program at unit couplings) against the oracle at
+    points that vary both alpha_s and kappa."""
+    lib = hostlib()
+    mom = np.ascontiguousarray(generate_events(name, n))
+    kap = [1.0, 0.0, 2.5] + list(kappa_points(3))
+    als = [ALS, ALS, 0.09, 0.118, 0.13, 0.2]
+    pts = np.array([[np.sqrt(4 * np.pi * a), k] for a, k in zip(als, kap)]).ravel()
+    me = np.zeros((len(kap), n))
+    assert lib.mgrw_host_qcd_me_kpoly(ng, _dp(mom), ctypes.c_int64(n), ctypes.c_double(MT), _dp(pts), len(kap),
+                                      _dp(me)) == 0
+    ref = oracle.qcd_me(ng, mom, [(a, MT, k) for a, k in zip(als, kap)])
+    assert np.all(me[1] == 0) and np.all(ref[1] == 0)      # every diagram has a top-gluon vertex
+    ok = np.arange(len(kap)) != 1
+    assert np.max(np.abs(me[ok] / ref[ok] - 1)) < 1e-12
+
+
+@pytest.mark.parametrize("ng,name", [(2, "gg_tt"), (3, "gg_ttg")])
+def test_oracle_me_is_polynomial_in_kappa(ng, name):
+    """|M|^2 is a polynomial in kappa with powers 2..2 ng only: fitted through
+    2 ng - 1 points it predicts the oracle elsewhere."""
+    mom = np.ascontiguousarray(generate_events(name, 8))
+    fit = np.linspace(0.5, 1.5, 2 * ng - 1)
+    test = [0.3, 1.9, -0.7]
+    me = oracle.qcd_me(ng, mom, [(ALS, MT, k) for k in list(fit) + test])
+    V = np.array([[k ** p for p in range(2, 2 * ng + 1)] for k in fit])
+    coef = np.linalg.solve(V, me[:len(fit)])
+    pred = np.array([[k ** p for p in range(2, 2 * ng + 1)] for k in test]) @ coef
+    assert np.max(np.abs(pred / me[len(fit):] - 1)) < 1e-9
+
+
+def test_kappa_polynomial_flop_counts_recorded():
+    path = os.path.join(B.GEN, "flops.json")
+    if not os.path.exists(path):
+        pytest.skip("not built")
+    f = json.load(open(path))
+    for name, ng, K in (("gg_tt", 2, 2), ("gg_ttg", 3, 6), ("gg_ttgg", 4, 24)):
+        kf = f[name]["kpoly_per_helicity_flops"]
+        # more than one plain program (ng colour products, ng(ng+1)/2 dot products)
+        assert f[name]["per_helicity_flops"] < kf < 2 * f[name]["per_helicity_flops"] + ng * 4 * K * K
