@@ -71,6 +71,8 @@ def _lib(quad=False):
     getattr(lib, p + "ee_mumu_me").argtypes = [dp, ctypes.c_int64, ctypes.POINTER(EwPoint),
                                                ctypes.c_int, dp]
     getattr(lib, p + "ee_mumu_amp").argtypes = [dp, ip, ctypes.POINTER(EwPoint), dp]
+    getattr(lib, p + "ee_photons_me").argtypes = [ctypes.c_int, dp, ctypes.c_int64, dp, ctypes.c_int, dp]
+    getattr(lib, p + "ee_photons_amp").argtypes = [ctypes.c_int, dp, ip, ctypes.c_double, ctypes.c_int, dp]
     getattr(lib, p + "reweight").argtypes = [dp, ctypes.c_int, ctypes.c_int64, dp, dp]
     getattr(lib, p + "wavefunction").argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, dp]
     _LIBS[quad] = (lib, p)
@@ -154,6 +156,26 @@ def ee_mumu_amp(mom_event, hel, point, quad=False):
     out = np.zeros(2)
     _call(quad, "ee_mumu_amp", _dp(m), h.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
           ew_points([point]), _dp(out))
+    return complex(out[0], out[1])
+
+
+def ee_photons_me(mom, alphas, quad=False):
+    """|M|^2 of e+ e- -> n photons, n = mom.shape[0] - 2, for each alpha: [len(alphas), n_events]."""
+    mom = np.ascontiguousarray(mom, dtype=np.float64)
+    n = mom.shape[2]
+    a = np.ascontiguousarray(alphas, dtype=np.float64)
+    out = np.zeros((len(a), n))
+    _call(quad, "ee_photons_me", mom.shape[0] - 2, _dp(mom), n, _dp(a), len(a), _dp(out))
+    return out
+
+
+def ee_photons_amp(mom_event, hel, alpha, gauge_leg=-1, quad=False):
+    """One helicity amplitude of e+ e- -> n photons; mom_event [n+2, 4]."""
+    m = np.ascontiguousarray(mom_event, dtype=np.float64).reshape(-1)
+    h = np.ascontiguousarray(hel, dtype=np.int32)
+    out = np.zeros(2)
+    _call(quad, "ee_photons_amp", len(h) - 2, _dp(m), h.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+          float(alpha), int(gauge_leg), _dp(out))
     return complex(out[0], out[1])
 
 

@@ -11,6 +11,7 @@
  *    incoming partons, colour-averaged, summed over all outgoing helicities and
  *    colours, with the symmetry factor of identical outgoing gluons (Sec. 2.1,
  *    eq. (1) names |M|^2 as the amplitude factor of the event weight);
+ *  - |M|^2 of e+ e- -> n photons (massless QED, all n! diagrams written out);
  *  - the reweighted weight W' = W |M'|^2 / |M|^2 (Sec. 2.2, eq. (3)), quiet NaN
  *    where |M|^2 = 0 (the validity condition stated with eq. (3)).
  *
@@ -611,6 +612,107 @@ int API(ee_mumu_amp)(const double *mom_aos, const int *hel, const orc_ew_point *
     R p[4][4];
     for (int i = 0; i < 4; ++i) for (int mu = 0; mu < 4; ++mu) p[i][mu] = mom_aos[i * 4 + mu];
     C a = ee_mumu_amp((const R(*)[4])p, hel, pt);
+    out[0] = (double)CRE(a);
+    out[1] = (double)CIM(a);
+    return 0;
+}
+
+/* ------------------------------------------------ e+ e- -> n photons (QED)
+ *
+ * e+(p0) e-(p1) -> gamma(p2) ... gamma(p_{n+1}) with a massless electron.
+ * Each of the n! Feynman diagrams attaches the photons to the electron line in
+ * one order s_1 .. s_n (counted from the electron end):
+ *   M_s = vbar(p0) V_{s_n} S(q_{n-1}) V_{s_{n-1}} ... V_{s_2} S(q_1) V_{s_1} u(p1),
+ *   q_j = p1 - k_{s_1} - ... - k_{s_j},  V_i = -i e Q eps_i*-slash (Q = -1),
+ *   S(q) = i qslash / q^2,
+ * and M is the sum over all n! orders, each written out as its own product.
+ * gauge_leg >= 0 replaces that photon's polarisation by its momentum (the
+ * Ward identity makes the amplitude vanish). */
+
+#define MAXA 6
+
+static int next_perm(int *a, int n) {          /* lexicographic successor */
+    int i = n - 2;
+    while (i >= 0 && a[i] >= a[i + 1]) --i;
+    if (i < 0) return 0;
+    int j = n - 1;
+    while (a[j] <= a[i]) --j;
+    int t = a[i]; a[i] = a[j]; a[j] = t;
+    for (int l = i + 1, r = n - 1; l < r; ++l, --r) { t = a[l]; a[l] = a[r]; a[r] = t; }
+    return 1;
+}
+
+static C ee_photons_amp(int na, const R p[][4], const int *hel, R e, int gauge_leg) {
+    S4 vb = bar(spinor_v(p[0], 0, hel[0]));     /* incoming e+ */
+    S4 u = spinor_u(p[1], 0, hel[1]);           /* incoming e- */
+    const R Q = -1;
+    M4 V[MAXA];
+    for (int i = 0; i < na; ++i) {
+        C eps[4];
+        if (i == gauge_leg) {
+            for (int mu = 0; mu < 4; ++mu) eps[mu] = p[2 + i][mu];
+        } else {
+            V4 ev = polvec(p[2 + i], hel[2 + i], 1);
+            for (int mu = 0; mu < 4; ++mu) eps[mu] = ev.c[mu];
+        }
+        M4 sl = slash_c(eps);
+        V[i] = m4_add(m4_zero(), sl, -I_C * e * Q);
+    }
+    int perm[MAXA];
+    for (int i = 0; i < na; ++i) perm[i] = i;
+    C amp = 0;
+    do {
+        S4 psi = u;
+        R q[4];
+        for (int mu = 0; mu < 4; ++mu) q[mu] = p[1][mu];
+        for (int j = 0; j < na; ++j) {
+            psi = times_col(V[perm[j]], psi);
+            if (j + 1 < na) {
+                for (int mu = 0; mu < 4; ++mu) q[mu] -= p[2 + perm[j]][mu];
+                M4 prop = m4_add(m4_zero(), slash_r(q), I_C / dot_rr(q, q));
+                psi = times_col(prop, psi);
+            }
+        }
+        amp += row_col(vb, psi);
+    } while (next_perm(perm, na));
+    return amp;
+}
+
+/* |M|^2 of e+ e- -> na photons for every event and every alpha: all 2^(na+2)
+ * helicity configurations summed, averaged over the 4 initial spins, divided
+ * by na! for the identical photons.  mom: [na+2][4][n] (SoA). */
+int API(ee_photons_me)(int na, const double *mom, int64_t n, const double *alpha, int npts, double *me) {
+    if (na < 1 || na > MAXA || n < 0 || npts < 1) return -1;
+    const int next = na + 2;
+    R fact = 1;
+    for (int i = 2; i <= na; ++i) fact *= i;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t ev = 0; ev < n; ++ev) {
+        R p[MAXA + 2][4];
+        for (int i = 0; i < next; ++i)
+            for (int mu = 0; mu < 4; ++mu) p[i][mu] = mom[((int64_t)i * 4 + mu) * n + ev];
+        for (int k = 0; k < npts; ++k) {
+            R e = RSQRT(4 * PI_R * (R)alpha[k]);
+            R acc = 0;
+            for (int h = 0; h < (1 << next); ++h) {
+                int hel[MAXA + 2];
+                for (int i = 0; i < next; ++i) hel[i] = (h >> (next - 1 - i) & 1) ? 1 : -1;
+                C a = ee_photons_amp(na, (const R(*)[4])p, hel, e, -1);
+                acc += CRE(a * CONJ(a));
+            }
+            me[(int64_t)k * n + ev] = (double)(acc / 4 / fact);
+        }
+    }
+    return 0;
+}
+
+/* One helicity amplitude (hel[i] = +-1 in particle order), out = (re, im). */
+int API(ee_photons_amp)(int na, const double *mom_aos, const int *hel, double alpha, int gauge_leg,
+                        double *out) {
+    if (na < 1 || na > MAXA) return -1;
+    R p[MAXA + 2][4];
+    for (int i = 0; i < na + 2; ++i) for (int mu = 0; mu < 4; ++mu) p[i][mu] = mom_aos[i * 4 + mu];
+    C a = ee_photons_amp(na, (const R(*)[4])p, hel, RSQRT(4 * PI_R * (R)alpha), gauge_leg);
     out[0] = (double)CRE(a);
     out[1] = (double)CIM(a);
     return 0;

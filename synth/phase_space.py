@@ -17,6 +17,9 @@ Recipes (one per workload):
 * ``gg_ttgg``   sqrt(s) = 1.5 TeV, massive RAMBO, gluon pT > 20 GeV and
                 Delta R(g, g) > 0.4 (pseudorapidity, azimuth wrapped to pi).
 * ``gg_ttggg``  sqrt(s) = 2 TeV, same cuts over all gluon pairs.
+* ``ee_5a``     e+ e- -> 5 photons at sqrt(s) = 1 TeV, massless RAMBO, photon
+                pT > 10 GeV, |eta| < 2.5 and Delta R(a, a) > 0.4 (the usual
+                default photon cuts of LO generators).
 
 RAMBO is the algorithm of Kleiss, Stirling and Ellis (Comput. Phys. Commun. 40
 (1986) 359): isotropic massless momenta with energies -ln(u u'), boosted and
@@ -54,6 +57,7 @@ class ProcessSpec:
     n_events: int        # full sample size of the workload
     pt_min: float = 0.0
     dr_min: float = 0.0
+    eta_max: float = None
 
     @property
     def seed(self):
@@ -66,6 +70,7 @@ PROCESSES = {
     "gg_ttg": ProcessSpec("gg_ttg", 3, 5, 3, (MT, MT, 0.0), 1500.0, 1 << 22, 20.0, 0.0),
     "gg_ttgg": ProcessSpec("gg_ttgg", 4, 6, 4, (MT, MT, 0.0, 0.0), 1500.0, 1 << 23, 20.0, 0.4),
     "gg_ttggg": ProcessSpec("gg_ttggg", 5, 7, 5, (MT, MT, 0.0, 0.0, 0.0), 2000.0, 1 << 20, 20.0, 0.4),
+    "ee_5a": ProcessSpec("ee_5a", 6, 7, 0, (0.0,) * 5, 1000.0, 1 << 22, 10.0, 0.4, 2.5),
 }
 
 
@@ -146,13 +151,17 @@ def _rambo_attempt(seed, ev, attempt, sqrt_s, masses):
     return p
 
 
-def _cuts(p_gluons, pt_min, dr_min):
-    """Acceptance mask for outgoing gluons p_gluons (ng, 4, n)."""
+def _cuts(p_gluons, pt_min, dr_min, eta_max=None):
+    """Acceptance mask for the outgoing massless partons p_gluons (ng, 4, n)."""
     ok = np.ones(p_gluons.shape[2], dtype=bool)
     if p_gluons.shape[0] == 0:
         return ok
     pt = np.hypot(p_gluons[:, 1], p_gluons[:, 2])
     ok &= np.all(pt > pt_min, axis=0)
+    if eta_max is not None:
+        pabs = np.sqrt(pt ** 2 + p_gluons[:, 3] ** 2)
+        eta = 0.5 * np.log((pabs + p_gluons[:, 3]) / np.maximum(pabs - p_gluons[:, 3], 1e-300))
+        ok &= np.all(np.abs(eta) < eta_max, axis=0)
     if dr_min > 0 and p_gluons.shape[0] > 1:
         pabs = np.sqrt(pt ** 2 + p_gluons[:, 3] ** 2)
         eta = 0.5 * np.log((pabs + p_gluons[:, 3]) / np.maximum(pabs - p_gluons[:, 3], 1e-300))
@@ -167,7 +176,7 @@ def _cuts(p_gluons, pt_min, dr_min):
 
 
 def rambo_massive(n, seed, sqrt_s, masses, pt_min=0.0, dr_min=0.0, first_event=0,
-                  n_massive_leading=2, max_attempts=10000):
+                  n_massive_leading=2, max_attempts=10000, eta_max=None):
     """Massive RAMBO in the CM frame with gluon cuts by rejection.
 
     `masses` are the outgoing masses; particles after the first
@@ -182,7 +191,7 @@ def rambo_massive(n, seed, sqrt_s, masses, pt_min=0.0, dr_min=0.0, first_event=0
             break
         ev = (pending + first_event).astype(np.uint64)
         p = _rambo_attempt(seed, ev, attempt, float(sqrt_s), masses)
-        ok = _cuts(p[n_massive_leading:], pt_min, dr_min)
+        ok = _cuts(p[n_massive_leading:], pt_min, dr_min, eta_max)
         acc = pending[ok]
         out[2:, :, acc] = p[:, :, ok]
         pending = pending[~ok]
@@ -199,8 +208,18 @@ def generate_events(proc, n, first_event=0, seed=None):
         return ee_mumu(n, seed, first_event, spec.sqrt_s)
     if proc == "gg_tt":
         return gg_tt(n, seed, first_event)
+    if proc == "ee_5a":
+        return rambo_massive(n, seed, spec.sqrt_s, spec.masses, spec.pt_min, spec.dr_min,
+                             first_event=first_event, n_massive_leading=0, eta_max=spec.eta_max)
     return rambo_massive(n, seed, spec.sqrt_s, spec.masses, spec.pt_min, spec.dr_min,
                          first_event=first_event)
+
+
+def alpha_points(n_points=16, seed=6000, alpha0=1 / 132.5, lo=0.5, hi=1.5):
+    """`n_points` iid draws of the electromagnetic coupling, uniform in
+    [lo, hi] * alpha0 (a random non-zero value per reweight iteration)."""
+    u = uniform(seed, STREAM_KAPPA, np.arange(n_points, dtype=np.uint64), 0)
+    return alpha0 * (lo + (hi - lo) * u)
 
 
 def kappa_points(n_points=16, seed=1000, lo=0.8, hi=1.2):
