@@ -21,6 +21,7 @@ sys.path.insert(0, HERE)
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (the packed rate)
 PEAK_FP64_TFLOPS = 78.6
 HBM_TBS = 8.0
+ALPHA0 = 1 / 132.5
 
 
 # HBM traffic of the exact kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
@@ -46,6 +47,7 @@ def log(*a):
 def flops_per_event(proc, n_points_total, n_hel):
     path = os.path.join(HERE, "paper_2312_07440_amd", "csrc", "gen", "flops.json")
     f = json.load(open(path))[proc]
+    n_hel = f.get("evaluated_helicities", n_hel)
     return n_points_total * n_hel * f["per_helicity_flops"], f
 
 
@@ -53,9 +55,11 @@ def cpu_baseline(proc, ng, mom_np, kap, gpu_out, sample, points_per_event):
     """The oracle (FP64, OpenMP) on a bounded sample of the same workload."""
     import oracle
     sub = np.ascontiguousarray(mom_np[:, :, :sample])
-    pts = [(0.118, 173.0, 1.0)] + [(0.118, 173.0, float(k)) for k in kap]
     t0 = time.perf_counter()
-    me = oracle.qcd_me(ng, sub, pts)
+    if proc == "ee_5a":
+        me = oracle.ee_photons_me(sub, [ALPHA0] + [float(a) for a in kap])
+    else:
+        me = oracle.qcd_me(ng, sub, [(0.118, 173.0, 1.0)] + [(0.118, 173.0, float(k)) for k in kap])
     w = oracle.reweight(me)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -116,7 +120,8 @@ def kpoly_leg(args, proc, mom, exact_out, stream, torch):
     torch.cuda.synchronize()
     ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
     f = json.load(open(os.path.join(HERE, "paper_2312_07440_amd", "csrc", "gen", "flops.json")))[args.proc]
-    fpe = proc.n_hel * f["kpoly_per_helicity_flops"]
+    fpe = (f["evaluated_helicities"] * f["per_helicity_flops"] if args.proc == "ee_5a"
+           else proc.n_hel * f["kpoly_per_helicity_flops"])
     achieved = fpe * args.n / (ms * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
     diff = float(torch.abs(kout / exact_out - 1.0).max())
@@ -153,16 +158,21 @@ def main():
 
     import torch
     import paper_2312_07440_amd as mg
-    from synth import generate_events, kappa_points
+    from synth import alpha_points, generate_events, kappa_points
 
-    ng = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}[args.proc]
+    ng = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5, "ee_5a": 0}[args.proc]
     log(f"generating {args.n} {args.proc} events")
     mom_np = generate_events(args.proc, args.n)
-    kap = kappa_points(args.points)
     dev = torch.device("cuda:0")
     mom = torch.from_numpy(mom_np).to(dev)
-    proc = mg.Process(args.proc, args.prec)
-    proc.set_params([{"kappa_ttg": float(k)} for k in kap])
+    if args.proc == "ee_5a":
+        kap = alpha_points(args.points)
+        proc = mg.Process(args.proc, args.prec, {"alpha": ALPHA0})
+        proc.set_params([{"alpha": float(a)} for a in kap])
+    else:
+        kap = kappa_points(args.points)
+        proc = mg.Process(args.proc, args.prec)
+        proc.set_params([{"kappa_ttg": float(k)} for k in kap])
     out = torch.empty((args.points, args.n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -211,18 +221,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.prec == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.proc} exact reweight, {args.n} events, {args.points} kappa points "
-                               f"+ base, {args.prec} precision",
+        "config": {"workload": f"{args.proc} exact reweight, {args.n} events, {args.points} "
+                               f"{'alpha' if args.proc == 'ee_5a' else 'kappa'} points + base, {args.prec} precision",
                    "events": args.n, "points": args.points, "process": args.proc,
                    "precision": args.prec, "path": "exact"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "flops_per_event": fpe, "per_helicity_flops": fcounts["per_helicity_flops"]},
     }
-    if not args.no_kpoly and args.proc in ("gg_tt", "gg_ttg", "gg_ttgg"):
+    if not args.no_kpoly and args.proc in ("gg_tt", "gg_ttg", "gg_ttgg", "ee_5a"):
         log("kappa-polynomial variant")
         res["kpoly"] = kpoly_leg(args, proc, mom, out, stream, torch)
-    if not args.no_surrogate:
+    if not args.no_surrogate and args.proc != "ee_5a":
         res["surrogate"] = surrogate_leg(args, proc, mom, out, kap, torch, generate_events)
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, args.n)

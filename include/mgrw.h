@@ -52,13 +52,17 @@ enum {
 typedef int mgrw_status;
 
 /* Processes (tree level, Standard Model couplings; kappa scales every
- * top-top-gluon vertex). */
+ * top-top-gluon vertex).  Particle order in the momentum array: as written,
+ * e.g. (e+, e-, mu+, mu-), (g, g, t, tbar, g, ...), (e+, e-, a, a, a, a, a). */
 enum {
     MGRW_EE_MUMU = 1,    /* e+ e- -> mu+ mu- via photon and Z           */
     MGRW_GG_TT = 2,      /* g g -> t tbar                               */
     MGRW_GG_TTG = 3,     /* g g -> t tbar g                             */
     MGRW_GG_TTGG = 4,    /* g g -> t tbar g g                           */
-    MGRW_GG_TTGGG = 5    /* g g -> t tbar g g g                         */
+    MGRW_GG_TTGGG = 5,   /* g g -> t tbar g g g                         */
+    MGRW_EE_5A = 6       /* e+ e- -> 5 photons, massless electron (the
+                            process of the paper's timing study, Table 1);
+                            120 diagrams; parameter: alpha            */
 };
 
 /* Arithmetic of the amplitude chains. */
@@ -143,10 +147,19 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
  * MGRW_MAP_EVENT_PER_LANE (one event per lane, helicities in a loop), or
  * MGRW_MAP_EVENT_PER_WAVE (one event per 64-lane wave, helicity
  * configurations on the lanes; processes with a multiple of 64 helicity
- * configurations only).  Results agree to rounding.  Errors: MGRW_ERR_ARG
- * (unknown option or value), MGRW_ERR_UNSUPPORTED (mapping not available for
- * the process). */
-enum { MGRW_OPT_LANE_MAPPING = 1 };
+ * configurations only).  Results agree to rounding.
+ *
+ * MGRW_OPT_RESCUE_PPM (mixed precision, g g -> t tbar + 0..2 g): events in
+ * which a gluon pair other than the two beams has |2 p_i.p_j| / s below
+ * value * 1e-6 are evaluated a second time in FP64 and their results
+ * replaced.  There the diagrams cancel strongly and single-precision
+ * amplitudes lose up to about three more digits.  Default 3000 (3e-3) for
+ * mixed-precision handles of those processes, 0 (off) otherwise; 0..1000000.
+ * Applies to mgrw_eval_me, mgrw_reweight and mgrw_reweight_kpoly.
+ *
+ * Errors: MGRW_ERR_ARG (unknown option or value), MGRW_ERR_UNSUPPORTED
+ * (mapping or rescue not available for the process or precision). */
+enum { MGRW_OPT_LANE_MAPPING = 1, MGRW_OPT_RESCUE_PPM = 2 };
 enum { MGRW_MAP_AUTO = 0, MGRW_MAP_EVENT_PER_LANE = 1, MGRW_MAP_EVENT_PER_WAVE = 2 };
 mgrw_status mgrw_set_option(mgrw_process *p, int option, int64_t value);
 

@@ -11,12 +11,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmgrw.so")
 
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_DEVICE, ERR_ALLOC, ERR_STATE = 0, -1, -2, -3, -4, -5
-EE_MUMU, GG_TT, GG_TTG, GG_TTGG, GG_TTGGG = 1, 2, 3, 4, 5
+EE_MUMU, GG_TT, GG_TTG, GG_TTGG, GG_TTGGG, EE_5A = 1, 2, 3, 4, 5, 6
 FP64, MIXED = 0, 1
 MAX_POINTS = 64
 
 PROCESS_IDS = {"ee_mumu": EE_MUMU, "gg_tt": GG_TT, "gg_ttg": GG_TTG, "gg_ttgg": GG_TTGG,
-               "gg_ttggg": GG_TTGGG}
+               "gg_ttggg": GG_TTGGG, "ee_5a": EE_5A}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 
 
@@ -179,6 +179,11 @@ class Process:
         """'auto', 'event_per_lane' or 'event_per_wave'."""
         v = {"auto": 0, "event_per_lane": 1, "event_per_wave": 2}[mapping]
         check(lib().mgrw_set_option(self._h, 1, v))
+
+    def set_rescue_threshold(self, tau):
+        """FP64 re-evaluation of events with a gluon invariant |2 p_i.p_j|/s < tau
+        (mixed precision; 0 switches it off).  Stored in units of 1e-6."""
+        check(lib().mgrw_set_option(self._h, 2, int(round(tau * 1e6))))
 
     def _n(self, mom):
         if mom.dim() != 3 or mom.shape[0] != self.n_ext or mom.shape[1] != 4:

@@ -42,7 +42,8 @@ def build(verbose=False, jobs=None):
     from .gen import generate, translation_units
     generate()
     os.makedirs(OBJ, exist_ok=True)
-    units = [os.path.join(CSRC, "mgrw_abi.hip"), os.path.join(CSRC, "mgrw_mlp.hip")] + \
+    units = [os.path.join(CSRC, "mgrw_abi.hip"), os.path.join(CSRC, "mgrw_mlp.hip"),
+             os.path.join(CSRC, "mgrw_qed.hip")] + \
         [os.path.join(GEN, u) for u in translation_units()]
     # the split program parts take longest: start them first
     units.sort(key=lambda u: ("_part" not in u, u))
@@ -78,6 +79,8 @@ def write_flops():
         kf = lib.mgrw_host_kpoly_flops(ng)
         if kf > 0:
             out[name]["kpoly_per_helicity_flops"] = kf
+    lib.mgrw_host_ee5a_flops.restype = ctypes.c_longlong
+    out["ee_5a"] = {"per_helicity_flops": lib.mgrw_host_ee5a_flops(), "evaluated_helicities": 64}
     with open(os.path.join(GEN, "flops.json"), "w") as f:
         json.dump(out, f, indent=1)
     return out

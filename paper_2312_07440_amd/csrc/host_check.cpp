@@ -10,6 +10,7 @@
 #include <cstring>
 
 #include "mgrw_event.h"
+#include "mgrw_qed.h"
 #include "gen/gg_tt.inc"
 #include "gen/gg_ttg.inc"
 #include "gen/gg_ttgg.inc"
@@ -147,6 +148,43 @@ long long mgrw_host_kpoly_flops(int ng) {
         case 4: return count_kpoly<mgrw::gg_ttgg>();
         default: return -1;
     }
+}
+
+// e+ e- -> 5 photons, |M|^2 for every alpha in alphas; mom SoA [7][4][n].
+int mgrw_host_ee5a_me(const double* mom, int64_t n, const double* alphas, int npts, double* me) {
+    using Proc = mgrw::ee_5a;
+    if (n < 0 || npts < 1) return -1;
+    for (int64_t e = 0; e < n; ++e) {
+        double p[Proc::NEXT][4];
+        for (int i = 0; i < Proc::NEXT; ++i)
+            for (int m = 0; m < 4; ++m) p[i][m] = mom[(int64_t(i) * 4 + m) * n + e];
+        Proc::event<double> ev;
+        Proc::setup(p, ev);
+        for (int k = 0; k < npts; ++k) {
+            const double ec = std::sqrt(4.0 * M_PI * alphas[k]);
+            double acc = 0.0;
+            for (int h = 0; h < Proc::NLIVE; ++h) {
+                mgrw::cx<double> a = Proc::amplitude<double>(ev, h, ec);
+                acc += a.re * a.re + a.im * a.im;
+            }
+            me[int64_t(k) * n + e] = acc * ev.flux * Proc::NORM;
+        }
+    }
+    return 0;
+}
+
+// add + mul of one live helicity configuration of e+ e- -> 5 photons
+long long mgrw_host_ee5a_flops() {
+    using Proc = mgrw::ee_5a;
+    double p[Proc::NEXT][4];
+    for (int i = 0; i < Proc::NEXT; ++i)
+        for (int m = 0; m < 4; ++m) p[i][m] = 1.0 + i + 0.25 * m;
+    Proc::event<cfloat> ev;
+    Proc::setup(p, ev);
+    cfloat::n_add = cfloat::n_mul = 0;
+    mgrw::cx<cfloat> a = Proc::amplitude<cfloat>(ev, 37, cfloat(0.3));
+    (void)a;
+    return cfloat::n_add + cfloat::n_mul + 3;   // + |a|^2
 }
 
 int mgrw_host_qcd_flops(int ng, long long* counts) {

@@ -34,6 +34,10 @@ MGRW_DECLARE_LAUNCHER(gg_tt)
 MGRW_DECLARE_LAUNCHER(gg_ttg)
 MGRW_DECLARE_LAUNCHER(gg_ttgg)
 MGRW_DECLARE_LAUNCHER(gg_ttggg)
+namespace mgrw {
+hipError_t launch_ee5a(int fp64, const double* mom, const double* w_in, int64_t n, const qed_launch& a, double* out,
+                       double* me0, hipStream_t s);
+}
 
 namespace {
 
@@ -80,6 +84,7 @@ struct proc_info {
 proc_info info_of(int proc) {
     switch (proc) {
         case MGRW_EE_MUMU: return {4, 1, 4, 2};
+        case MGRW_EE_5A: return {7, 1, 128, 120};
         case MGRW_GG_TT: return {mgrw::gg_tt::NEXT, mgrw::gg_tt::K, mgrw::gg_tt::NHEL, mgrw::gg_tt::NDIAG};
         case MGRW_GG_TTG: return {mgrw::gg_ttg::NEXT, mgrw::gg_ttg::K, mgrw::gg_ttg::NHEL, mgrw::gg_ttg::NDIAG};
         case MGRW_GG_TTGG:
@@ -94,7 +99,9 @@ mgrw_status check_params(int proc, const mgrw_params& q, const char* what) {
     const double v[8] = {q.alpha, q.sw2, q.mz, q.wz, q.alphas, q.mt, q.wt, q.kappa_ttg};
     for (double x : v)
         if (!finite(x)) return fail(MGRW_ERR_ARG, std::string(what) + ": non-finite parameter");
-    if (proc == MGRW_EE_MUMU) {
+    if (proc == MGRW_EE_5A) {
+        if (!(q.alpha > 0)) return fail(MGRW_ERR_ARG, std::string(what) + ": need alpha > 0");
+    } else if (proc == MGRW_EE_MUMU) {
         if (!(q.alpha > 0) || !(q.sw2 > 0 && q.sw2 < 1) || !(q.mz > 0) || !(q.wz >= 0))
             return fail(MGRW_ERR_ARG, std::string(what) + ": need alpha > 0, 0 < sw2 < 1, mz > 0, wz >= 0");
     } else {
@@ -147,6 +154,16 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
     if ((st = check_device_ptr(w_in, "w_in", true)) != MGRW_OK) return st;
     if ((st = check_device_ptr(me0, "me_base_out", true)) != MGRW_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->proc == MGRW_EE_5A) {
+        qed_launch a;
+        std::memset(&a, 0, sizeof a);
+        for (int k = 0; k < npts; ++k) a.e[k] = std::sqrt(4.0 * M_PI * pts[k].alpha);
+        a.npts = npts;
+        a.mode = mode;
+        a.kpoly = kpoly;
+        if ((n + 3) / 4 > 0x7fffffffLL) return fail(MGRW_ERR_ARG, "n_events too large for one launch");
+        return launched(launch_ee5a(p->prec == MGRW_FP64, mom, w_in, n, a, out, me0, s));
+    }
     if (p->proc == MGRW_EE_MUMU) {
         ew_launch a;
         std::memset(&a, 0, sizeof a);
@@ -174,6 +191,7 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
     a.mapping = p->mapping != MGRW_MAP_AUTO ? p->mapping
                 : (info_of(p->proc).n_hel % 64 == 0 ? MGRW_MAP_EVENT_PER_WAVE : MGRW_MAP_EVENT_PER_LANE);
     a.kpoly = kpoly;
+    a.rescue_tau = p->rescue_tau;
     const int fp64 = p->prec == MGRW_FP64;
     switch (p->proc) {
         case MGRW_GG_TT: return launched(launch_gg_tt(fp64, mom, w_in, n, a, out, me0, s));
@@ -192,7 +210,7 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     if (!out) return fail(MGRW_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!base) return fail(MGRW_ERR_ARG, "base is NULL");
-    if (proc < MGRW_EE_MUMU || proc > MGRW_GG_TTGGG) return fail(MGRW_ERR_ARG, "unknown process");
+    if (proc < MGRW_EE_MUMU || proc > MGRW_EE_5A) return fail(MGRW_ERR_ARG, "unknown process");
     if (prec != MGRW_FP64 && prec != MGRW_MIXED) return fail(MGRW_ERR_ARG, "unknown precision");
     if (info_of(proc).n_ext == 0) return fail(MGRW_ERR_UNSUPPORTED, "process not built into this library");
     if (proc == MGRW_EE_MUMU && prec != MGRW_FP64)
@@ -208,6 +226,7 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     p->base = *base;
     p->n_points = 0;
     p->mapping = MGRW_MAP_AUTO;
+    p->rescue_tau = (prec == MGRW_MIXED && proc >= MGRW_GG_TT && proc <= MGRW_GG_TTGG) ? 3e-3 : 0.0;
     p->sur = nullptr;
     *out = p;
     return MGRW_OK;
@@ -220,7 +239,7 @@ mgrw_status mgrw_set_params(mgrw_process* p, const mgrw_params* points, int32_t 
     for (int k = 0; k < n_points; ++k) {
         mgrw_status st = check_params(p->proc, points[k], "point");
         if (st != MGRW_OK) return st;
-        if (p->proc != MGRW_EE_MUMU && points[k].mt != p->base.mt)
+        if (p->proc != MGRW_EE_MUMU && p->proc != MGRW_EE_5A && points[k].mt != p->base.mt)
             return fail(MGRW_ERR_ARG, "external masses must equal the base point's");
     }
     std::memcpy(p->points, points, sizeof(mgrw_params) * size_t(n_points));
@@ -252,7 +271,8 @@ mgrw_status mgrw_reweight_kpoly(mgrw_process* p, const double* mom, const double
                                 double* w_out, double* me_base_out, void* stream) {
     if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
     if (p->proc == MGRW_EE_MUMU || p->proc == MGRW_GG_TTGGG)
-        return fail(MGRW_ERR_UNSUPPORTED, "kappa-polynomial reweighting: g g -> t tbar + 0..2 g only");
+        return fail(MGRW_ERR_UNSUPPORTED,
+                    "kappa-polynomial reweighting: g g -> t tbar + 0..2 g and e+ e- -> 5 photons only");
     if (p->n_points == 0) return fail(MGRW_ERR_STATE, "no parameter points set");
     mgrw_params all[kMaxLaunchPoints];
     all[0] = p->base;
@@ -272,12 +292,19 @@ mgrw_status mgrw_process_info(const mgrw_process* p, int* n_ext, int* n_flows, i
 
 mgrw_status mgrw_set_option(mgrw_process* p, int option, int64_t value) {
     if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
+    if (option == MGRW_OPT_RESCUE_PPM) {
+        if (value < 0 || value > 1000000) return fail(MGRW_ERR_ARG, "rescue threshold must be 0..1000000 ppm");
+        if (value != 0 && (p->prec != MGRW_MIXED || p->proc < MGRW_GG_TT || p->proc > MGRW_GG_TTGG))
+            return fail(MGRW_ERR_UNSUPPORTED, "FP64 rescue: mixed precision g g -> t tbar + 0..2 g only");
+        p->rescue_tau = double(value) * 1e-6;
+        return MGRW_OK;
+    }
     if (option != MGRW_OPT_LANE_MAPPING) return fail(MGRW_ERR_ARG, "unknown option");
     if (value != MGRW_MAP_AUTO && value != MGRW_MAP_EVENT_PER_LANE && value != MGRW_MAP_EVENT_PER_WAVE)
         return fail(MGRW_ERR_ARG, "unknown lane mapping");
     if (value == MGRW_MAP_EVENT_PER_WAVE && (p->proc == MGRW_EE_MUMU || info_of(p->proc).n_hel % 64 != 0))
         return fail(MGRW_ERR_UNSUPPORTED, "one event per wave needs a multiple of 64 helicity configurations");
-    if (value == MGRW_MAP_EVENT_PER_LANE && p->proc == MGRW_GG_TTGGG)
+    if (value == MGRW_MAP_EVENT_PER_LANE && (p->proc == MGRW_GG_TTGGG || p->proc == MGRW_EE_5A))
         return fail(MGRW_ERR_UNSUPPORTED, "g g -> t tbar g g g runs one event per wave only");
     p->mapping = int(value);
     return MGRW_OK;

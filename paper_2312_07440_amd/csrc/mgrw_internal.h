@@ -18,5 +18,6 @@ struct mgrw_process {
     mgrw_params points[MGRW_MAX_POINTS];
     int n_points;
     int mapping;                        // MGRW_MAP_*
+    double rescue_tau;                  // FP64 rescue threshold on |2 p_i.p_j|/s (0: off)
     mgrw::surrogate* sur;               // null until trained or loaded
 };

@@ -23,12 +23,21 @@ struct qcd_launch {
     double mt;
     int mapping;     // MGRW_MAP_EVENT_PER_LANE or MGRW_MAP_EVENT_PER_WAVE
     int kpoly;       // 1: kappa-polynomial evaluation (one program per helicity for all points)
+    double rescue_tau;   // > 0: events with a gluon invariant |2 p_i.p_j|/s below it are redone in FP64
 };
 
 struct ew_launch {
     mgrw::ew_point pts[kMaxLaunchPoints];
     int npts;
     int mode;
+};
+
+// e+ e- -> n photons: the coupling e = sqrt(4 pi alpha) of every point.
+struct qed_launch {
+    double e[kMaxLaunchPoints];
+    int npts;
+    int mode;
+    int kpoly;       // 1: one evaluation at e = 1, |M|^2 = e^(2n) |M_1|^2 for every point
 };
 
 template <int NEXT>
@@ -261,6 +270,149 @@ hipError_t launch_kpoly(const double* mom, const double* w_in, int64_t n, const 
     }
 }
 
+// ------------------------------------- FP64 rescue of ill-conditioned events
+//
+// In single precision the helicity amplitudes lose digits where diagrams
+// cancel strongly against each other: a final-state gluon nearly collinear to
+// a beam gluon or to another final-state gluon (small |2 p_i.p_j| / s).  After
+// the single-precision pass, events with such an invariant below a threshold
+// are listed and evaluated again in double precision, one event per wave,
+// overwriting their results.
+
+template <class Proc>
+__device__ __forceinline__ bool ill_conditioned(const double (&p)[Proc::NEXT][4], double tau) {
+    const double E = p[0][0] + p[1][0], X = p[0][1] + p[1][1], Y = p[0][2] + p[1][2], Z = p[0][3] + p[1][3];
+    const double s = E * E - X * X - Y * Y - Z * Z;
+    bool ill = false;
+    // gluons: the beams (particles 0 and 1) and the final state (4 ...)
+#pragma unroll
+    for (int i = 0; i < Proc::NEXT; ++i) {
+#pragma unroll
+        for (int j = i + 1; j < Proc::NEXT; ++j) {
+            const bool gi = i < 2 || i >= 4, gj = j < 2 || j >= 4;
+            if (!gi || !gj || (i == 0 && j == 1)) continue;
+            const double d = p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] - p[i][3] * p[j][3];
+            ill = ill || (fabs(2.0 * d) < tau * s);
+        }
+    }
+    return ill;
+}
+
+template <class Proc>
+__global__ void rescue_reset_kernel(unsigned long long* count) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) count[0] = 0;
+}
+
+template <class Proc>
+__global__ void __launch_bounds__(kBlock)
+rescue_flag_kernel(const double* __restrict__ mom, int64_t n, double tau, unsigned long long* __restrict__ count,
+                   int64_t* __restrict__ list) {
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n) return;
+    double p[Proc::NEXT][4];
+    load_event<Proc::NEXT>(mom, n, e, p);
+    if (ill_conditioned<Proc>(p, tau)) list[atomicAdd(count, 1ull)] = e;
+}
+
+// Grid-stride over the listed events; each wave takes one event at a time and
+// every wave leaves the loop once the list is exhausted.
+template <class Proc, bool KP>
+__global__ void __launch_bounds__(kBlock, 1)
+qcd_rescue_kernel(const double* __restrict__ mom, const int64_t* __restrict__ list,
+                  const unsigned long long* __restrict__ count, const double* __restrict__ w_in, int64_t n,
+                  qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
+    __shared__ event_data<Proc, double> sh[kBlock / 64];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t cnt = int64_t(count[0]);
+    const int64_t stride = int64_t(gridDim.x) * (kBlock / 64);
+    event_data<Proc, double>& d = sh[wv];
+#pragma unroll 1
+    for (int64_t i = int64_t(blockIdx.x) * (kBlock / 64) + wv; i < cnt; i += stride) {
+        const int64_t e = list[i];
+        if (lane == 0) {
+            double p[Proc::NEXT][4];
+            load_event<Proc::NEXT>(mom, n, e, p);
+            Proc::kinematics(p, a.mt, d.k);
+            Proc::external_basis(p, a.mt, d.b);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
+        if constexpr (KP) {
+            double B[kpoly_pairs<Proc>()] = {};
+#pragma unroll 1
+            for (int hc = 0; hc < Proc::NHEL; hc += 64)
+                if (hc + lane < Proc::NHEL) kpoly_helicity<Proc, double>(d.k, d.b, hc + lane, B);
+#pragma unroll
+            for (int q = 0; q < kpoly_pairs<Proc>(); ++q) B[q] = wave_sum(B[q]);
+            if (lane == 0) kpoly_outputs<Proc>(B, a, n, e, w, out, me0_out);
+        } else {
+            double me0 = 0.0;
+#pragma unroll 1
+            for (int kp = 0; kp < a.npts; ++kp) {
+                const qcd_point pt = a.pts[kp];
+                typename Proc::template coup<double> c = {pt.gs, pt.gs2, pt.gk};
+                double acc = 0.0;
+#pragma unroll 1
+                for (int hc = 0; hc < Proc::NHEL; hc += 64) {
+                    if (hc + lane < Proc::NHEL) {
+                        typename Proc::template ext<double> wf;
+                        Proc::template external<double>(d.b, hc + lane, wf);
+                        cx<double> J[Proc::K];
+                        Proc::amplitude(wf, d.k, c, J);
+                        acc += Proc::colour_sum(J);
+                    }
+                }
+                const double me = wave_sum(acc) * Proc::NORM;
+                if (kp == 0) {
+                    me0 = me;
+                    if (lane == 0) {
+                        if (a.mode == 1)
+                            out[e] = me;
+                        else if (me0_out)
+                            me0_out[e] = me;
+                    }
+                } else if (lane == 0) {
+                    out[int64_t(kp - 1) * n + e] = reweighted(w, me, me0);
+                }
+            }
+        }
+        // every lane has read the slot before the next event overwrites it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+constexpr unsigned kRescueBlocks = 1024;
+
+template <class Proc>
+hipError_t launch_rescue(const double* mom, const double* w_in, int64_t n, const qcd_launch& a, double* out,
+                         double* me0, hipStream_t s) {
+    if constexpr (Proc::NEXT <= 4) {
+        return hipSuccess;   // no final-state gluon
+    } else {
+        int64_t* buf = nullptr;
+        hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&buf), sizeof(int64_t) * size_t(n + 1), s);
+        if (err != hipSuccess) return err;
+        unsigned long long* count = reinterpret_cast<unsigned long long*>(buf);
+        int64_t* list = buf + 1;
+        hipLaunchKernelGGL((rescue_reset_kernel<Proc>), dim3(1), dim3(64), 0, s, count);
+        hipLaunchKernelGGL((rescue_flag_kernel<Proc>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           mom, n, a.rescue_tau, count, list);
+        if (a.kpoly)
+            hipLaunchKernelGGL((qcd_rescue_kernel<Proc, true>), dim3(kRescueBlocks), dim3(kBlock), 0, s, mom, list,
+                               count, w_in, n, a, out, me0);
+        else
+            hipLaunchKernelGGL((qcd_rescue_kernel<Proc, false>), dim3(kRescueBlocks), dim3(kBlock), 0, s, mom, list,
+                               count, w_in, n, a, out, me0);
+        err = hipGetLastError();
+        hipError_t ferr = hipFreeAsync(buf, s);
+        return err != hipSuccess ? err : ferr;
+    }
+}
+
 // ------------------------------------------- programs split over kernels
 //
 // For the largest process the per-helicity program is split into NCHUNK
@@ -368,8 +520,8 @@ hipError_t launch_wave(const double* mom, const double* w_in, int64_t n, const q
 }
 
 template <class Proc>
-hipError_t launch_qcd(int fp64, const double* mom, const double* w_in, int64_t n, const qcd_launch& a,
-                      double* out, double* me0, hipStream_t s) {
+hipError_t launch_main(int fp64, const double* mom, const double* w_in, int64_t n, const qcd_launch& a,
+                       double* out, double* me0, hipStream_t s) {
     if (a.kpoly)
         return fp64 ? launch_kpoly<Proc, double>(mom, w_in, n, a, out, me0, s)
                     : launch_kpoly<Proc, float>(mom, w_in, n, a, out, me0, s);
@@ -382,6 +534,14 @@ hipError_t launch_qcd(int fp64, const double* mom, const double* w_in, int64_t n
     else
         hipLaunchKernelGGL((qcd_kernel<Proc, float>), dim3(blocks), dim3(kBlock), 0, s, mom, w_in, n, a, out, me0);
     return hipGetLastError();
+}
+
+template <class Proc>
+hipError_t launch_qcd(int fp64, const double* mom, const double* w_in, int64_t n, const qcd_launch& a,
+                      double* out, double* me0, hipStream_t s) {
+    hipError_t err = launch_main<Proc>(fp64, mom, w_in, n, a, out, me0, s);
+    if (err != hipSuccess || fp64 || !(a.rescue_tau > 0.0)) return err;
+    return launch_rescue<Proc>(mom, w_in, n, a, out, me0, s);
 }
 
 }  // namespace mgrw

@@ -554,7 +554,8 @@ void adam(surrogate* s, float lr, hipStream_t st) {
 }
 
 mgrw_status check_qcd_kappa_only(const mgrw_process* p) {
-    if (p->proc == MGRW_EE_MUMU) return set_error(MGRW_ERR_UNSUPPORTED, "surrogate: QCD processes only");
+    if (p->proc == MGRW_EE_MUMU || p->proc == MGRW_EE_5A)
+        return set_error(MGRW_ERR_UNSUPPORTED, "surrogate: QCD processes only");
     if (p->n_points == 0) return set_error(MGRW_ERR_STATE, "no parameter points set");
     for (int k = 0; k < p->n_points; ++k) {
         const mgrw_params& q = p->points[k];

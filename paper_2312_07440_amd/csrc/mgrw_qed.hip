@@ -1,0 +1,90 @@
+// Kernels of e+ e- -> 5 photons: one event per 64-lane wave, the 64
+// non-vanishing helicity configurations on the lanes.  The event's
+// helicity-independent data (propagator vectors q_S / q_S^2 of the 30 proper
+// photon subsets, polarisation bases, e+ e- spinors) are built once per event
+// in double precision by a setup kernel and read by the waves through the
+// scalar cache.
+#include <hip/hip_runtime.h>
+
+#include "mgrw_kernels.h"
+#include "mgrw_qed.h"
+
+namespace mgrw {
+
+namespace {
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+ee5a_setup_kernel(const double* __restrict__ mom, int64_t n, ee_5a::event<T>* __restrict__ ev) {
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n) return;
+    double p[ee_5a::NEXT][4];
+    load_event<ee_5a::NEXT>(mom, n, e, p);
+    ee_5a::setup(p, ev[e]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+ee5a_wave_kernel(const ee_5a::event<T>* __restrict__ ev, const double* __restrict__ w_in, int64_t n, qed_launch a,
+                 double* __restrict__ out, double* __restrict__ me0_out) {
+    static_assert(ee_5a::NLIVE == 64, "one live helicity configuration per lane");
+    const int64_t e = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (e >= n) return;   // whole wave; no barriers below
+    const int lane = threadIdx.x & 63;
+    const ee_5a::event<T>& d = ev[e];
+    const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
+    const double scale = d.flux * ee_5a::NORM;
+    double me0 = 0.0;
+    double me1 = 0.0;   // |M|^2 at e = 1 (coupling-polynomial mode)
+    if (a.kpoly) {
+        const cx<T> amp = ee_5a::amplitude<T>(d, lane, T(1));
+        me1 = wave_sum(double(amp.re) * double(amp.re) + double(amp.im) * double(amp.im)) * scale;
+    }
+#pragma unroll 1
+    for (int kp = 0; kp < a.npts; ++kp) {
+        double me;
+        if (a.kpoly) {
+            const double e2 = a.e[kp] * a.e[kp];
+            me = me1 * (e2 * e2 * e2 * e2 * e2);
+        } else {
+            __asm__ volatile("" ::: "memory");
+            const cx<T> amp = ee_5a::amplitude<T>(d, lane, T(a.e[kp]));
+            me = wave_sum(double(amp.re) * double(amp.re) + double(amp.im) * double(amp.im)) * scale;
+        }
+        if (kp == 0) {
+            me0 = me;
+            if (lane == 0) {
+                if (a.mode == 1)
+                    out[e] = me;
+                else if (me0_out)
+                    me0_out[e] = me;
+            }
+        } else if (lane == 0) {
+            out[int64_t(kp - 1) * n + e] = reweighted(w, me, me0);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch(const double* mom, const double* w_in, int64_t n, const qed_launch& a, double* out, double* me0,
+                  hipStream_t s) {
+    ee_5a::event<T>* ev = nullptr;
+    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(ee_5a::event<T>) * size_t(n), s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((ee5a_setup_kernel<T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, mom,
+                       n, ev);
+    hipLaunchKernelGGL((ee5a_wave_kernel<T>), dim3(unsigned((n + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
+                       s, ev, w_in, n, a, out, me0);
+    err = hipGetLastError();
+    hipError_t ferr = hipFreeAsync(ev, s);
+    return err != hipSuccess ? err : ferr;
+}
+
+}  // namespace
+
+hipError_t launch_ee5a(int fp64, const double* mom, const double* w_in, int64_t n, const qed_launch& a,
+                       double* out, double* me0, hipStream_t s) {
+    return fp64 ? launch<double>(mom, w_in, n, a, out, me0, s) : launch<float>(mom, w_in, n, a, out, me0, s);
+}
+
+}  // namespace mgrw

@@ -132,3 +132,18 @@ def test_kappa_polynomial_flop_counts_recorded():
         kf = f[name]["kpoly_per_helicity_flops"]
         # more than one plain program (ng colour products, ng(ng+1)/2 dot products)
         assert f[name]["per_helicity_flops"] < kf < 2 * f[name]["per_helicity_flops"] + ng * 4 * K * K
+
+
+def test_host_photon_recursion_matches_oracle():
+    """The subset recursion of e+ e- -> 5 photons (Weyl spinors, 64 live
+    helicity configurations) against the oracle's explicit sum over the 120
+    diagrams and all 128 configurations."""
+    from synth import alpha_points
+    lib = hostlib()
+    n = 24
+    mom = np.ascontiguousarray(generate_events("ee_5a", n))
+    al = np.array([1 / 132.5] + list(alpha_points(3)))
+    me = np.zeros((len(al), n))
+    assert lib.mgrw_host_ee5a_me(_dp(mom), ctypes.c_int64(n), _dp(al), len(al), _dp(me)) == 0
+    ref = oracle.ee_photons_me(mom, al)
+    assert np.max(np.abs(me / ref - 1)) < 1e-12
