@@ -157,11 +157,23 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
  * mixed-precision handles of those processes, 0 (off) otherwise; 0..1000000.
  * Applies to mgrw_eval_me, mgrw_reweight and mgrw_reweight_kpoly.
  *
+ * MGRW_OPT_KERNEL_TIMING (0 or 1): when 1, every launch records a pair of HIP
+ * events on its stream around its amplitude kernel(s) (after the setup of
+ * the kinematics, before the FP64 re-evaluation), read by
+ * mgrw_kernel_time_ms.
+ *
  * Errors: MGRW_ERR_ARG (unknown option or value), MGRW_ERR_UNSUPPORTED
- * (mapping or rescue not available for the process or precision). */
-enum { MGRW_OPT_LANE_MAPPING = 1, MGRW_OPT_RESCUE_PPM = 2 };
+ * (mapping or rescue not available for the process or precision),
+ * MGRW_ERR_DEVICE (event creation failed). */
+enum { MGRW_OPT_LANE_MAPPING = 1, MGRW_OPT_RESCUE_PPM = 2, MGRW_OPT_KERNEL_TIMING = 3 };
 enum { MGRW_MAP_AUTO = 0, MGRW_MAP_EVENT_PER_LANE = 1, MGRW_MAP_EVENT_PER_WAVE = 2 };
 mgrw_status mgrw_set_option(mgrw_process *p, int option, int64_t value);
+
+/* Device time in ms of the amplitude kernel(s) of the handle's most recent
+ * launch (kernel timing on); waits for that launch to finish.  Errors:
+ * MGRW_ERR_STATE (timing off or nothing launched since it was switched on),
+ * MGRW_ERR_DEVICE. */
+mgrw_status mgrw_kernel_time_ms(mgrw_process *p, double *ms);
 
 /* Release the handle (NULL is ignored).  Work already launched with it is
  * unaffected: its parameters travelled with the launch. */

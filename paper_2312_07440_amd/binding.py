@@ -99,6 +99,8 @@ def lib():
     L.mgrw_reweight_kpoly.argtypes = [vp, dp, dp, i64, dp, dp, vp]
     L.mgrw_reweight_kpoly.restype = ctypes.c_int
     L.mgrw_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
+    L.mgrw_kernel_time_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.mgrw_kernel_time_ms.restype = ctypes.c_int
     L.mgrw_set_option.restype = ctypes.c_int
     _lib = L
     return L
@@ -179,6 +181,16 @@ class Process:
         """'auto', 'event_per_lane' or 'event_per_wave'."""
         v = {"auto": 0, "event_per_lane": 1, "event_per_wave": 2}[mapping]
         check(lib().mgrw_set_option(self._h, 1, v))
+
+    def set_kernel_timing(self, on=True):
+        """Record HIP events around the amplitude kernel(s) of every launch."""
+        check(lib().mgrw_set_option(self._h, 3, 1 if on else 0))
+
+    def kernel_time_ms(self):
+        """Device time of the amplitude kernel(s) of the most recent launch."""
+        v = ctypes.c_double()
+        check(lib().mgrw_kernel_time_ms(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_rescue_threshold(self, tau):
         """FP64 re-evaluation of events with a gluon invariant |2 p_i.p_j|/s < tau

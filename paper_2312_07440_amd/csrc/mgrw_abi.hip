@@ -161,6 +161,9 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
         a.npts = npts;
         a.mode = mode;
         a.kpoly = kpoly;
+        a.t0 = p->t0;
+        a.t1 = p->t1;
+        p->timed = p->t0 != nullptr;
         if ((n + 3) / 4 > 0x7fffffffLL) return fail(MGRW_ERR_ARG, "n_events too large for one launch");
         return launched(launch_ee5a(p->prec == MGRW_FP64, mom, w_in, n, a, out, me0, s));
     }
@@ -192,6 +195,9 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
                 : (info_of(p->proc).n_hel % 64 == 0 ? MGRW_MAP_EVENT_PER_WAVE : MGRW_MAP_EVENT_PER_LANE);
     a.kpoly = kpoly;
     a.rescue_tau = p->rescue_tau;
+    a.t0 = p->t0;
+    a.t1 = p->t1;
+    p->timed = p->t0 != nullptr;
     const int fp64 = p->prec == MGRW_FP64;
     switch (p->proc) {
         case MGRW_GG_TT: return launched(launch_gg_tt(fp64, mom, w_in, n, a, out, me0, s));
@@ -228,6 +234,8 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     p->mapping = MGRW_MAP_AUTO;
     p->rescue_tau = (prec == MGRW_MIXED && proc >= MGRW_GG_TT && proc <= MGRW_GG_TTGG) ? 3e-3 : 0.0;
     p->sur = nullptr;
+    p->t0 = p->t1 = nullptr;
+    p->timed = 0;
     *out = p;
     return MGRW_OK;
 }
@@ -299,6 +307,22 @@ mgrw_status mgrw_set_option(mgrw_process* p, int option, int64_t value) {
         p->rescue_tau = double(value) * 1e-6;
         return MGRW_OK;
     }
+    if (option == MGRW_OPT_KERNEL_TIMING) {
+        if (value != 0 && value != 1) return fail(MGRW_ERR_ARG, "kernel timing: 0 or 1");
+        if (value == 1 && !p->t0) {
+            if (hipEventCreate(&p->t0) != hipSuccess || hipEventCreate(&p->t1) != hipSuccess) {
+                if (p->t0) (void)hipEventDestroy(p->t0);
+                p->t0 = p->t1 = nullptr;
+                return fail(MGRW_ERR_DEVICE, "hipEventCreate failed");
+            }
+        } else if (value == 0 && p->t0) {
+            (void)hipEventDestroy(p->t0);
+            (void)hipEventDestroy(p->t1);
+            p->t0 = p->t1 = nullptr;
+        }
+        p->timed = 0;
+        return MGRW_OK;
+    }
     if (option != MGRW_OPT_LANE_MAPPING) return fail(MGRW_ERR_ARG, "unknown option");
     if (value != MGRW_MAP_AUTO && value != MGRW_MAP_EVENT_PER_LANE && value != MGRW_MAP_EVENT_PER_WAVE)
         return fail(MGRW_ERR_ARG, "unknown lane mapping");
@@ -310,8 +334,23 @@ mgrw_status mgrw_set_option(mgrw_process* p, int option, int64_t value) {
     return MGRW_OK;
 }
 
+mgrw_status mgrw_kernel_time_ms(mgrw_process* p, double* ms) {
+    if (!p || !ms) return fail(MGRW_ERR_ARG, "process or ms is NULL");
+    if (!p->t0 || !p->timed) return fail(MGRW_ERR_STATE, "kernel timing is off or nothing was launched");
+    float f = 0.0f;
+    hipError_t err = hipEventSynchronize(p->t1);
+    if (err == hipSuccess) err = hipEventElapsedTime(&f, p->t0, p->t1);
+    if (err != hipSuccess) return fail(MGRW_ERR_DEVICE, std::string("event timing: ") + hipGetErrorString(err));
+    *ms = double(f);
+    return MGRW_OK;
+}
+
 void mgrw_destroy_process(mgrw_process* p) {
     if (!p) return;
+    if (p->t0) {
+        (void)hipEventDestroy(p->t0);
+        (void)hipEventDestroy(p->t1);
+    }
     mgrw::surrogate_destroy(p->sur);
     delete p;
 }

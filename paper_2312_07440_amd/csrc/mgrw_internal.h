@@ -3,6 +3,8 @@
 
 #include <string>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/mgrw.h"
 
 namespace mgrw {
@@ -20,4 +22,6 @@ struct mgrw_process {
     int mapping;                        // MGRW_MAP_*
     double rescue_tau;                  // FP64 rescue threshold on |2 p_i.p_j|/s (0: off)
     mgrw::surrogate* sur;               // null until trained or loaded
+    hipEvent_t t0, t1;                  // amplitude-kernel timestamps (timing option), else null
+    int timed;                          // a launch has recorded t0/t1
 };

@@ -24,6 +24,7 @@ struct qcd_launch {
     int mapping;     // MGRW_MAP_EVENT_PER_LANE or MGRW_MAP_EVENT_PER_WAVE
     int kpoly;       // 1: kappa-polynomial evaluation (one program per helicity for all points)
     double rescue_tau;   // > 0: events with a gluon invariant |2 p_i.p_j|/s below it are redone in FP64
+    hipEvent_t t0, t1;   // non-null: recorded around the amplitude kernel(s) of the launch
 };
 
 struct ew_launch {
@@ -38,7 +39,13 @@ struct qed_launch {
     int npts;
     int mode;
     int kpoly;       // 1: one evaluation at e = 1, |M|^2 = e^(2n) |M_1|^2 for every point
+    hipEvent_t t0, t1;
 };
+
+// Device-side timestamps around the amplitude kernel(s) of a launch.
+inline void mark(hipEvent_t ev, hipStream_t s) {
+    if (ev) (void)hipEventRecord(ev, s);
+}
 
 template <int NEXT>
 __device__ __forceinline__ void load_event(const double* __restrict__ mom, int64_t n, int64_t e,
@@ -126,21 +133,54 @@ qcd_kernel(const double* __restrict__ mom, const double* __restrict__ w_in, int6
 #define MGRW_WAVE_WPE 2
 #endif
 
+// Single-precision amplitudes lose digits where diagrams cancel strongly
+// against each other: a final-state gluon nearly collinear to a beam gluon or
+// to another final-state gluon (small |2 p_i.p_j| / s).  Such events are
+// evaluated again in FP64 after the single-precision pass.
+template <class Proc>
+__device__ __forceinline__ bool ill_conditioned(const double (&p)[Proc::NEXT][4], double tau) {
+    const double E = p[0][0] + p[1][0], X = p[0][1] + p[1][1], Y = p[0][2] + p[1][2], Z = p[0][3] + p[1][3];
+    const double s = E * E - X * X - Y * Y - Z * Z;
+    bool ill = false;
+    // gluons: the beams (particles 0 and 1) and the final state (4 ...)
+#pragma unroll
+    for (int i = 0; i < Proc::NEXT; ++i) {
+#pragma unroll
+        for (int j = i + 1; j < Proc::NEXT; ++j) {
+            const bool gi = i < 2 || i >= 4, gj = j < 2 || j >= 4;
+            if (!gi || !gj || (i == 0 && j == 1)) continue;
+            const double d = p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] - p[i][3] * p[j][3];
+            ill = ill || (fabs(2.0 * d) < tau * s);
+        }
+    }
+    return ill;
+}
+
 template <class Proc, typename T>
 struct event_data {
     typename Proc::template kin<T> k;
     typename Proc::template basis<T> b;
+    int skip;   // 1: left to the FP64 re-evaluation
 };
 
+// Kinematics and wavefunction bases of every event; with tau > 0 also lists
+// the ill-conditioned events (count, list) and marks them to be skipped.
 template <class Proc, typename T>
 __global__ void __launch_bounds__(kBlock)
-qcd_setup_kernel(const double* __restrict__ mom, int64_t n, double mt, event_data<Proc, T>* __restrict__ ev) {
+qcd_setup_kernel(const double* __restrict__ mom, int64_t n, double mt, event_data<Proc, T>* __restrict__ ev,
+                 double tau, unsigned long long* __restrict__ count, int64_t* __restrict__ list) {
     const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (e >= n) return;
     double p[Proc::NEXT][4];
     load_event<Proc::NEXT>(mom, n, e, p);
     Proc::kinematics(p, mt, ev[e].k);
     Proc::external_basis(p, mt, ev[e].b);
+    int skip = 0;
+    if (tau > 0.0 && ill_conditioned<Proc>(p, tau)) {
+        skip = 1;
+        list[atomicAdd(count, 1ull)] = e;
+    }
+    ev[e].skip = skip;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -155,7 +195,7 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* __rest
                 qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
     static_assert(Proc::NHEL % 64 == 0, "helicity configurations must fill whole waves");
     const int64_t e = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (e >= n) return;   // whole wave; no barriers below
+    if (e >= n || ev[e].skip) return;   // whole wave; no barriers below
     const int lane = threadIdx.x & 63;
     const typename Proc::template kin<T>& k = ev[e].k;
     const typename Proc::template basis<T>& b = ev[e].b;
@@ -236,7 +276,7 @@ __global__ void __launch_bounds__(kBlock)
 qcd_kpoly_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* __restrict__ w_in, int64_t n,
                       qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
     const int64_t e = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (e >= n) return;
+    if (e >= n || ev[e].skip) return;   // whole wave
     const int lane = threadIdx.x & 63;
     double B[kpoly_pairs<Proc>()] = {};
 #pragma unroll 1
@@ -249,27 +289,6 @@ qcd_kpoly_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* 
     if (lane == 0) kpoly_outputs<Proc>(B, a, n, e, (a.mode == 0 && w_in) ? w_in[e] : 1.0, out, me0_out);
 }
 
-template <class Proc, typename T>
-hipError_t launch_kpoly(const double* mom, const double* w_in, int64_t n, const qcd_launch& a, double* out,
-                        double* me0, hipStream_t s) {
-    if constexpr (Proc::NHEL % 64 == 0) {
-        event_data<Proc, T>* ev = nullptr;
-        hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(event_data<Proc, T>) * size_t(n), s);
-        if (err != hipSuccess) return err;
-        hipLaunchKernelGGL((qcd_setup_kernel<Proc, T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, mom, n, a.mt, ev);
-        hipLaunchKernelGGL((qcd_kpoly_wave_kernel<Proc, T>), dim3(unsigned((n + kBlock / 64 - 1) / (kBlock / 64))),
-                           dim3(kBlock), 0, s, ev, w_in, n, a, out, me0);
-        err = hipGetLastError();
-        hipError_t ferr = hipFreeAsync(ev, s);
-        return err != hipSuccess ? err : ferr;
-    } else {
-        hipLaunchKernelGGL((qcd_kpoly_lane_kernel<Proc, T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock),
-                           0, s, mom, w_in, n, a, out, me0);
-        return hipGetLastError();
-    }
-}
-
 // ------------------------------------- FP64 rescue of ill-conditioned events
 //
 // In single precision the helicity amplitudes lose digits where diagrams
@@ -278,25 +297,6 @@ hipError_t launch_kpoly(const double* mom, const double* w_in, int64_t n, const 
 // the single-precision pass, events with such an invariant below a threshold
 // are listed and evaluated again in double precision, one event per wave,
 // overwriting their results.
-
-template <class Proc>
-__device__ __forceinline__ bool ill_conditioned(const double (&p)[Proc::NEXT][4], double tau) {
-    const double E = p[0][0] + p[1][0], X = p[0][1] + p[1][1], Y = p[0][2] + p[1][2], Z = p[0][3] + p[1][3];
-    const double s = E * E - X * X - Y * Y - Z * Z;
-    bool ill = false;
-    // gluons: the beams (particles 0 and 1) and the final state (4 ...)
-#pragma unroll
-    for (int i = 0; i < Proc::NEXT; ++i) {
-#pragma unroll
-        for (int j = i + 1; j < Proc::NEXT; ++j) {
-            const bool gi = i < 2 || i >= 4, gj = j < 2 || j >= 4;
-            if (!gi || !gj || (i == 0 && j == 1)) continue;
-            const double d = p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] - p[i][3] * p[j][3];
-            ill = ill || (fabs(2.0 * d) < tau * s);
-        }
-    }
-    return ill;
-}
 
 template <class Proc>
 __global__ void rescue_reset_kernel(unsigned long long* count) {
@@ -413,6 +413,60 @@ hipError_t launch_rescue(const double* mom, const double* w_in, int64_t n, const
     }
 }
 
+// One event per wave: per-event data (in single precision with the rescue
+// on, also the list of ill-conditioned events, which the amplitude kernel
+// skips), the amplitude kernel, then the FP64 re-evaluation of the listed
+// events.  KP: kappa-polynomial evaluation.
+template <class Proc, typename T, bool KP>
+hipError_t launch_wave_pipeline(const double* mom, const double* w_in, int64_t n, const qcd_launch& a, double* out,
+                                double* me0, hipStream_t s) {
+    const bool rescue = sizeof(T) == 4 && a.rescue_tau > 0.0 && Proc::NEXT > 4;
+    event_data<Proc, T>* ev = nullptr;
+    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(event_data<Proc, T>) * size_t(n), s);
+    if (err != hipSuccess) return err;
+    int64_t* buf = nullptr;
+    if (rescue) {
+        err = hipMallocAsync(reinterpret_cast<void**>(&buf), sizeof(int64_t) * size_t(n + 1), s);
+        if (err != hipSuccess) {
+            (void)hipFreeAsync(ev, s);
+            return err;
+        }
+    }
+    unsigned long long* count = rescue ? reinterpret_cast<unsigned long long*>(buf) : nullptr;
+    int64_t* list = rescue ? buf + 1 : nullptr;
+    if (rescue) hipLaunchKernelGGL((rescue_reset_kernel<Proc>), dim3(1), dim3(64), 0, s, count);
+    hipLaunchKernelGGL((qcd_setup_kernel<Proc, T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       mom, n, a.mt, ev, rescue ? a.rescue_tau : 0.0, count, list);
+    const dim3 grid(unsigned((n + kBlock / 64 - 1) / (kBlock / 64)));
+    mark(a.t0, s);
+    if constexpr (KP)
+        hipLaunchKernelGGL((qcd_kpoly_wave_kernel<Proc, T>), grid, dim3(kBlock), 0, s, ev, w_in, n, a, out, me0);
+    else
+        hipLaunchKernelGGL((qcd_wave_kernel<Proc, T>), grid, dim3(kBlock), 0, s, ev, w_in, n, a, out, me0);
+    mark(a.t1, s);
+    if (rescue)
+        hipLaunchKernelGGL((qcd_rescue_kernel<Proc, KP>), dim3(kRescueBlocks), dim3(kBlock), 0, s, mom, list, count,
+                           w_in, n, a, out, me0);
+    err = hipGetLastError();
+    hipError_t f1 = rescue ? hipFreeAsync(buf, s) : hipSuccess;
+    hipError_t f2 = hipFreeAsync(ev, s);
+    return err != hipSuccess ? err : (f1 != hipSuccess ? f1 : f2);
+}
+
+template <class Proc, typename T>
+hipError_t launch_kpoly(const double* mom, const double* w_in, int64_t n, const qcd_launch& a, double* out,
+                        double* me0, hipStream_t s) {
+    if constexpr (Proc::NHEL % 64 == 0) {
+        return launch_wave_pipeline<Proc, T, true>(mom, w_in, n, a, out, me0, s);
+    } else {
+        mark(a.t0, s);
+        hipLaunchKernelGGL((qcd_kpoly_lane_kernel<Proc, T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, s, mom, w_in, n, a, out, me0);
+        mark(a.t1, s);
+        return hipGetLastError();
+    }
+}
+
 // ------------------------------------------- programs split over kernels
 //
 // For the largest process the per-helicity program is split into NCHUNK
@@ -497,26 +551,15 @@ hipError_t launch_part(const event_data<Proc, T>* ev, int64_t e0, int64_t nb, T*
 // Events per batch of the split programs (bounds the HBM buffer for J).
 constexpr int64_t kPartBatch = 8192;
 
-// Launch the reweight (mode 0) or single-point (mode 1) kernel of Proc at the
+// Launch the reweight (mode 0) or single-point (mode 1) kernels of Proc at the
 // requested arithmetic; returns the launch status.
 template <class Proc, typename T>
 hipError_t launch_wave(const double* mom, const double* w_in, int64_t n, const qcd_launch& a, double* out,
                        double* me0, hipStream_t s) {
-    if constexpr (Proc::NHEL % 64 != 0) {
+    if constexpr (Proc::NHEL % 64 != 0)
         return hipErrorInvalidConfiguration;
-    } else {
-        // per-event scratch for kinematics and bases (stream-ordered allocation)
-        event_data<Proc, T>* ev = nullptr;
-        hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(event_data<Proc, T>) * size_t(n), s);
-        if (err != hipSuccess) return err;
-        hipLaunchKernelGGL((qcd_setup_kernel<Proc, T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, mom, n, a.mt, ev);
-        hipLaunchKernelGGL((qcd_wave_kernel<Proc, T>), dim3(unsigned((n + kBlock / 64 - 1) / (kBlock / 64))),
-                           dim3(kBlock), 0, s, ev, w_in, n, a, out, me0);
-        err = hipGetLastError();
-        hipError_t ferr = hipFreeAsync(ev, s);
-        return err != hipSuccess ? err : ferr;
-    }
+    else
+        return launch_wave_pipeline<Proc, T, false>(mom, w_in, n, a, out, me0, s);
 }
 
 template <class Proc>
@@ -529,10 +572,12 @@ hipError_t launch_main(int fp64, const double* mom, const double* w_in, int64_t 
         return fp64 ? launch_wave<Proc, double>(mom, w_in, n, a, out, me0, s)
                     : launch_wave<Proc, float>(mom, w_in, n, a, out, me0, s);
     const unsigned blocks = unsigned((n + kBlock - 1) / kBlock);
+    mark(a.t0, s);
     if (fp64)
         hipLaunchKernelGGL((qcd_kernel<Proc, double>), dim3(blocks), dim3(kBlock), 0, s, mom, w_in, n, a, out, me0);
     else
         hipLaunchKernelGGL((qcd_kernel<Proc, float>), dim3(blocks), dim3(kBlock), 0, s, mom, w_in, n, a, out, me0);
+    mark(a.t1, s);
     return hipGetLastError();
 }
 
@@ -541,6 +586,9 @@ hipError_t launch_qcd(int fp64, const double* mom, const double* w_in, int64_t n
                       double* out, double* me0, hipStream_t s) {
     hipError_t err = launch_main<Proc>(fp64, mom, w_in, n, a, out, me0, s);
     if (err != hipSuccess || fp64 || !(a.rescue_tau > 0.0)) return err;
+    // the one-event-per-wave pipelines re-evaluate their listed events themselves
+    const bool wave = a.kpoly ? Proc::NHEL % 64 == 0 : a.mapping == MGRW_MAP_EVENT_PER_WAVE;
+    if (wave) return err;
     return launch_rescue<Proc>(mom, w_in, n, a, out, me0, s);
 }
 

@@ -73,8 +73,10 @@ hipError_t launch(const double* mom, const double* w_in, int64_t n, const qed_la
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL((ee5a_setup_kernel<T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, mom,
                        n, ev);
+    mark(a.t0, s);
     hipLaunchKernelGGL((ee5a_wave_kernel<T>), dim3(unsigned((n + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
                        s, ev, w_in, n, a, out, me0);
+    mark(a.t1, s);
     err = hipGetLastError();
     hipError_t ferr = hipFreeAsync(ev, s);
     return err != hipSuccess ? err : ferr;

@@ -66,12 +66,14 @@ def generate(outdir=None, procs=None, force=False):
                     "    if (err != hipSuccess) return err;\n"
                     f"    err = hipMallocAsync(reinterpret_cast<void**>(&jbuf), sizeof(float) * size_t(B) * a.npts * 2 * {name}::K * {name}::NHEL, s);\n"
                     "    if (err != hipSuccess) { (void)hipFreeAsync(ev, s); return err; }\n"
-                    f"    hipLaunchKernelGGL((qcd_setup_kernel<{name}, float>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, mom, n, a.mt, ev);\n"
+                    f"    hipLaunchKernelGGL((qcd_setup_kernel<{name}, float>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, mom, n, a.mt, ev, 0.0, nullptr, nullptr);\n"
                     "    err = hipGetLastError();\n"
+                    "    mark(a.t0, s);\n"
                     "    for (int64_t e0 = 0; e0 < n && err == hipSuccess; e0 += B) {\n"
                     "        const int64_t nb = n - e0 < B ? n - e0 : B;\n"
                     f"{calls}\n"
                     "    }\n"
+                    "    mark(a.t1, s);\n"
                     "    hipError_t f1 = hipFreeAsync(jbuf, s), f2 = hipFreeAsync(ev, s);\n"
                     "    return err != hipSuccess ? err : (f1 != hipSuccess ? f1 : f2);\n}\n")
         put(os.path.join(outdir, f"qcd_{name}.hip"), head + body + "}  // namespace mgrw\n")

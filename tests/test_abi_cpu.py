@@ -72,3 +72,14 @@ def test_set_params_and_state_errors(L):
     # n = 0 is accepted and launches nothing
     assert L.mgrw_reweight(p._h, None, None, 0, None, None, None) == bd.OK
     p.close()
+
+
+def test_photon_process_info_and_option_errors(L):
+    p = bd.Process("ee_5a", "mixed", {"alpha": 1 / 132.5})
+    assert (p.n_ext, p.n_flows, p.n_hel, p.n_diagrams) == (7, 1, 128, 120)
+    with pytest.raises(bd.MgrwError):
+        p.set_rescue_threshold(1e-3)
+    with pytest.raises(bd.MgrwError):
+        p.set_params([{"alpha": -1.0}])
+    with pytest.raises(bd.MgrwError):
+        p.kernel_time_ms()                      # timing is off

@@ -328,3 +328,29 @@ def test_gg_ttggg_full_configuration_uneven_batches(torch_dev):
     e = relerr(out[:, idx], w_ref)
     say(f"  batches {sizes}; sampled W' rel err max {e.max():.3e} median {np.median(e):.3e}")
     assert e.max() <= TOL["mixed"]
+
+
+def test_kernel_timing(torch_dev):
+    """HIP events recorded by the library around its amplitude kernel lie
+    inside the caller's events around the whole call."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    say("case kernel timing gg_ttgg n=4096")
+    p = mg.Process("gg_ttgg", "mixed")
+    p.set_params([{"kappa_ttg": float(k)} for k in kappa_points(4)])
+    mom = to_dev(torch, generate_events("gg_ttgg", 4096))
+    with pytest.raises(RuntimeError):
+        p.kernel_time_ms()
+    p.set_kernel_timing(True)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    p.reweight(mom)
+    e.record()
+    t = p.kernel_time_ms()
+    torch.cuda.synchronize()
+    step = s.elapsed_time(e)
+    say(f"  kernel {t:.3f} ms, call {step:.3f} ms")
+    assert 0 < t <= step
+    p.set_kernel_timing(False)
+    with pytest.raises(RuntimeError):
+        p.kernel_time_ms()
