@@ -24,19 +24,26 @@ HBM_TBS = 8.0
 ALPHA0 = 1 / 132.5
 
 
-# HBM traffic of the exact kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
-# (copy-calibrated; see profiles/), valid only for the kernel sources it was
-# measured on: keyed by a fingerprint of those sources.
-MEASURED_TRAFFIC = {("gg_ttgg", "mixed", "e5f9ba7e41a2cd56"): 1794833.0}   # bytes per event per launch
-KERNEL_SOURCES = ["paper_2312_07440_amd/csrc/mgrw_kernels.h", "paper_2312_07440_amd/csrc/mgrw_lorentz.h",
-                  "paper_2312_07440_amd/csrc/mgrw_event.h", "paper_2312_07440_amd/gen/process.py"]
+# HBM traffic of the exact amplitude kernel measured with rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (copy-calibrated; see profiles/), valid only for the sources that
+# kernel is built from: keyed by a fingerprint of those sources.
+MEASURED_TRAFFIC = {}   # (proc, prec, fingerprint) -> bytes per event per launch
+WAVE_SECTION = ("// ------------------------------------------------ one event per wave",
+                "// ------------------------------------------------ kappa-polynomial kernels")
 
 
-def kernel_fingerprint():
+def kernel_fingerprint(proc="gg_ttgg"):
+    """sha256 prefix of the one-event-per-wave kernel section of mgrw_kernels.h,
+    the Lorentz and event headers and the generated program of the process."""
     import hashlib
     h = hashlib.sha256()
-    for s in KERNEL_SOURCES:
-        h.update(open(os.path.join(HERE, s), "rb").read())
+    csrc = os.path.join(HERE, "paper_2312_07440_amd", "csrc")
+    if not os.path.exists(os.path.join(csrc, "gen", f"{proc}.inc")):
+        return None
+    k = open(os.path.join(csrc, "mgrw_kernels.h")).read()
+    h.update(k[k.index(WAVE_SECTION[0]):k.index(WAVE_SECTION[1])].encode())
+    for f in ("mgrw_lorentz.h", "mgrw_event.h", os.path.join("gen", f"{proc}.inc")):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -215,7 +222,7 @@ def main():
     achieved = fpe * args.n / (kms * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
     value = args.n * args.points / (ms * 1e-3)
-    tb = MEASURED_TRAFFIC.get((args.proc, args.prec, kernel_fingerprint()))
+    tb = MEASURED_TRAFFIC.get((args.proc, args.prec, kernel_fingerprint(args.proc)))
     traffic = None if tb is None else tb * args.n
 
     res = {

@@ -117,33 +117,29 @@ struct ee_photons {
         ev.flux = 4.0 * p[0][0] * p[1][0];
     }
 
-    template <typename T>
-    static MGRW_HD T flip(T x, bool neg) {
-        return neg ? -x : x;
-    }
-
     // Amplitude (up to the common phase, without the flux factor) of live
     // configuration h: bit NA gives the e- label (1: +1), bit i < NA the
     // helicity of photon i (1: +1); the e+ label is the opposite of the e-
-    // one.  e: the electromagnetic coupling at every vertex.
+    // one.  e: the electromagnetic coupling at every vertex.  The helicity
+    // signs enter as factors +-1, which the compiler folds into the products.
     template <typename T, typename EV>
     static MGRW_HD cx<T> amplitude(const EV& ev, int h, T e) {
-        const bool sp = (h >> NA) & 1;   // e- label +1 (s = +1)
-        const int li = sp ? 0 : 1;
-        // vertex matrices V_i = -s e eps*.sigma = [[va, vb], [vc, -va]] with
-        // eps* = (-l e1 + i e2)/sqrt2 for photon helicity l: the real parts
-        // carry the sign s l, the imaginary parts -s
+        const int lam = (h >> NA) & 1 ? 1 : -1;
+        const T s = T(lam);
+        const int li = lam > 0 ? 0 : 1;
+        // vertex matrices V_i = -s e eps*.sigma = [[va, vb], [vc, -va]],
+        // eps* = (-l e1 + i e2)/sqrt2 for photon helicity l
         cx<T> va[NA], vb[NA], vc[NA];
-        const T g = e * T(0.70710678118654752440);
+        const T r2 = T(0.70710678118654752440);
 #if defined(__HIP_DEVICE_COMPILE__)
 #pragma unroll
 #endif
         for (int i = 0; i < NA; ++i) {
-            const bool lp = (h >> i) & 1;
-            const bool nre = sp != lp, nim = sp;
-            const cx<T> ex = {flip(ev.e1[i][0] * g, nre), flip(ev.e2[i][0] * g, nim)};
-            const cx<T> ey = {flip(ev.e1[i][1] * g, nre), flip(ev.e2[i][1] * g, nim)};
-            const cx<T> ez = {flip(ev.e1[i][2] * g, nre), flip(ev.e2[i][2] * g, nim)};
+            const T l = (h >> i) & 1 ? T(1) : T(-1);
+            const T f = -s * e * r2;
+            const cx<T> ex = {-l * ev.e1[i][0] * f, ev.e2[i][0] * f};
+            const cx<T> ey = {-l * ev.e1[i][1] * f, ev.e2[i][1] * f};
+            const cx<T> ez = {-l * ev.e1[i][2] * f, ev.e2[i][2] * f};
             va[i] = ez;
             vb[i] = {ex.re + ey.im, ex.im - ey.re};   // ex - i ey
             vc[i] = {ex.re - ey.im, ex.im + ey.re};   // ex + i ey
@@ -165,8 +161,7 @@ struct ee_photons {
                 ub = ub + vc[i] * x.a - va[i] * x.b;
             }
             // P(q) = [[A + sZ, s(X - iY)], [s(X + iY), A - sZ]] with (A, X, Y, Z) = q / q^2
-            const T A = ev.P[mask][0];
-            const T X = flip(ev.P[mask][1], !sp), Y = flip(ev.P[mask][2], !sp), Z = flip(ev.P[mask][3], !sp);
+            const T A = ev.P[mask][0], X = s * ev.P[mask][1], Y = s * ev.P[mask][2], Z = s * ev.P[mask][3];
             const cx<T> xmy = {X, -Y}, xpy = {X, Y};
             R[mask] = {(A + Z) * ua + xmy * ub, xpy * ua + (A - Z) * ub};
         }
