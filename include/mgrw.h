@@ -179,6 +179,54 @@ mgrw_status mgrw_kernel_time_ms(mgrw_process *p, double *ms);
  * unaffected: its parameters travelled with the launch. */
 void mgrw_destroy_process(mgrw_process *p);
 
+/* One reweight over a sample that mixes processes, such as the Born and
+ * real-emission configurations of an NLO sample (g g -> t tbar and
+ * g g -> t tbar g; the same tree-level machinery evaluates both, Sec. 4).
+ * procs[0..n_procs-1] (1..8 handles, all with the same number of points P);
+ * proc_index[e] (device, int32) selects event e's process; mom (device) holds
+ * n_ext_max momentum rows per event, mom[(i*4+mu)*N + e], of which a process
+ * with n_ext particles reads rows 0..n_ext-1 in its own particle order.
+ * w_out [P][N] and me_base_out (nullable) as in mgrw_reweight; each event's
+ * results are those mgrw_reweight gives for it with its process's handle.
+ * The events of each process are gathered into a contiguous batch on the
+ * device and reweighted there; the call synchronises the stream once, to
+ * read the per-process counts.  Errors: MGRW_ERR_ARG (sizes, differing P,
+ * indices outside [0, n_procs)), MGRW_ERR_STATE, MGRW_ERR_DEVICE, and those of
+ * mgrw_reweight. */
+mgrw_status mgrw_multi_reweight(mgrw_process *const *procs, int n_procs, const double *mom, int n_ext_max,
+                                const int32_t *proc_index, const double *w_in, int64_t n_events, double *w_out,
+                                double *me_base_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Les Houches event files: steps 2 (events in) and 8 (weights out) of the
+ * reweighting procedure (Sec. 3.2).  Host memory, host code.
+ *
+ * mgrw_lhe_open reads a whole file; its text is kept so that mgrw_lhe_write
+ * reproduces every byte of it and only adds the new weights.
+ * mgrw_lhe_events fills mom[(i*4+mu)*N + e] (the layout of mgrw_reweight,
+ * host memory, N = mgrw_lhe_info's count) in the particle order of process
+ * proc: the event's incoming (status -1) and outgoing (status +1) particles
+ * are matched to the process's slots by PDG code in order of appearance
+ * (intermediate particles are skipped), and every event is boosted along the
+ * beam axis to the frame in which its incoming momenta sum to zero (the frame
+ * of the amplitudes' polarisation vectors).  w (nullable) receives each
+ * event's XWGTUP.  Errors: MGRW_ERR_ARG with the file, line or event and the
+ * reason (unreadable file, malformed event, particle content that does not
+ * match the process, incoming partons off the beam axis).
+ * mgrw_lhe_write writes the file with, in every event, one
+ * <wgt id='ids[k]'> w_new[k*N + e] </wgt> per point (17 significant digits)
+ * added to the event's <rwgt> block (created if absent) and the ids declared
+ * in the header's <initrwgt> block (created inside <header> if absent); it
+ * writes path.part and renames it, so a failed write leaves no partial file.
+ * Ids must be non-empty and free of quotes, markup and newlines. */
+typedef struct mgrw_lhe mgrw_lhe;
+mgrw_status mgrw_lhe_open(const char *path, mgrw_lhe **out);
+mgrw_status mgrw_lhe_info(const mgrw_lhe *h, int64_t *n_events);
+mgrw_status mgrw_lhe_events(const mgrw_lhe *h, int proc, double *mom, double *w);
+mgrw_status mgrw_lhe_write(const mgrw_lhe *h, const char *path, const double *w_new, int n_points,
+                           const char *const *ids);
+void mgrw_lhe_close(mgrw_lhe *h);
+
 /* ------------------------------------------------------------------------
  * Learned surrogate of the reweight factor.
  *

@@ -5,5 +5,5 @@ include/mgrw.h); this package is its Python binding plus the build-time
 process generator.
 """
 from .binding import (  # noqa: F401
-    Process, Params, make_params, MgrwError, PROCESS_IDS, PRECISIONS, MAX_POINTS, lib,
+    Process, Params, make_params, MgrwError, LHEFile, multi_reweight, PROCESS_IDS, PRECISIONS, MAX_POINTS, lib,
 )

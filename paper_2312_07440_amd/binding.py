@@ -98,6 +98,18 @@ def lib():
     L.mgrw_surrogate_fwd_bwd.restype = ctypes.c_int
     L.mgrw_reweight_kpoly.argtypes = [vp, dp, dp, i64, dp, dp, vp]
     L.mgrw_reweight_kpoly.restype = ctypes.c_int
+    L.mgrw_multi_reweight.argtypes = [ctypes.POINTER(vp), ctypes.c_int, dp, ctypes.c_int, vp, dp, i64, dp, dp, vp]
+    L.mgrw_multi_reweight.restype = ctypes.c_int
+    L.mgrw_lhe_open.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+    L.mgrw_lhe_open.restype = ctypes.c_int
+    L.mgrw_lhe_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.mgrw_lhe_info.restype = ctypes.c_int
+    L.mgrw_lhe_events.argtypes = [vp, ctypes.c_int, dp, dp]
+    L.mgrw_lhe_events.restype = ctypes.c_int
+    L.mgrw_lhe_write.argtypes = [vp, ctypes.c_char_p, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p)]
+    L.mgrw_lhe_write.restype = ctypes.c_int
+    L.mgrw_lhe_close.argtypes = [vp]
+    L.mgrw_lhe_close.restype = None
     L.mgrw_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int64]
     L.mgrw_kernel_time_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.mgrw_kernel_time_ms.restype = ctypes.c_int
@@ -286,3 +298,71 @@ class Process:
                                            grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                            ctypes.byref(loss), _stream(stream)))
         return pred, grad, loss.value
+
+
+def multi_reweight(processes, mom, proc_index, w_in=None, out=None, me_base_out=None, stream=None):
+    """mgrw_multi_reweight: one call over events of several processes.
+    mom [n_ext_max, 4, N] float64, proc_index [N] int32 (device tensors)."""
+    import torch
+    if mom.dim() != 3 or mom.shape[1] != 4:
+        raise ValueError("mom must have shape (n_ext_max, 4, n)")
+    n = mom.shape[2]
+    if not isinstance(proc_index, torch.Tensor) or not proc_index.is_cuda or proc_index.dtype != torch.int32 \
+            or not proc_index.is_contiguous() or proc_index.numel() != n:
+        raise ValueError("proc_index must be a contiguous int32 device tensor of n elements")
+    npts = processes[0].n_points
+    if out is None:
+        out = torch.empty((npts, n), dtype=torch.float64, device=mom.device)
+    arr = (ctypes.c_void_p * len(processes))(*[p._h.value for p in processes])
+    check(lib().mgrw_multi_reweight(arr, len(processes), _ptr(mom, "mom"), mom.shape[0],
+                                    ctypes.c_void_p(proc_index.data_ptr()), _ptr(w_in, "w_in", n, allow_none=True), n,
+                                    _ptr(out, "out", npts * n), _ptr(me_base_out, "me_base_out", n, allow_none=True),
+                                    _stream(stream)))
+    return out
+
+
+class LHEFile:
+    """A Les Houches event file read by libmgrw (mgrw_lhe_*): events in, new
+    weights out.  Host arrays (numpy)."""
+
+    def __init__(self, path):
+        h = ctypes.c_void_p()
+        check(lib().mgrw_lhe_open(os.fsencode(path), ctypes.byref(h)))
+        self._h = h
+
+    def __len__(self):
+        n = ctypes.c_int64()
+        check(lib().mgrw_lhe_info(self._h, ctypes.byref(n)))
+        return n.value
+
+    def events(self, proc):
+        """(mom [n_ext, 4, N] in the process's particle order and partonic
+        centre-of-mass frame, XWGTUP [N]) as float64 numpy arrays."""
+        import numpy as np
+        pid = PROCESS_IDS[proc] if isinstance(proc, str) else int(proc)
+        n_ext = {EE_MUMU: 4, GG_TT: 4, GG_TTG: 5, GG_TTGG: 6, GG_TTGGG: 7, EE_5A: 7}[pid]
+        n = len(self)
+        mom = np.empty((n_ext, 4, n))
+        w = np.empty(n)
+        check(lib().mgrw_lhe_events(self._h, pid, ctypes.c_void_p(mom.ctypes.data), ctypes.c_void_p(w.ctypes.data)))
+        return mom, w
+
+    def write(self, path, w_new, ids):
+        """Write the file with the weights w_new [P, N] added as <wgt id=ids[k]>."""
+        import numpy as np
+        w = np.ascontiguousarray(w_new, dtype=np.float64)
+        if w.ndim != 2 or w.shape[1] != len(self) or w.shape[0] != len(ids):
+            raise ValueError("w_new must have shape (len(ids), n_events)")
+        arr = (ctypes.c_char_p * len(ids))(*[str(i).encode() for i in ids])
+        check(lib().mgrw_lhe_write(self._h, os.fsencode(path), ctypes.c_void_p(w.ctypes.data), len(ids), arr))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgrw_lhe_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

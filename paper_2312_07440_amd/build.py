@@ -43,7 +43,7 @@ def build(verbose=False, jobs=None):
     generate()
     os.makedirs(OBJ, exist_ok=True)
     units = [os.path.join(CSRC, "mgrw_abi.hip"), os.path.join(CSRC, "mgrw_mlp.hip"),
-             os.path.join(CSRC, "mgrw_qed.hip")] + \
+             os.path.join(CSRC, "mgrw_qed.hip"), os.path.join(CSRC, "mgrw_multi.hip")] + \
         [os.path.join(GEN, u) for u in translation_units()]
     # the split program parts take longest: start them first
     units.sort(key=lambda u: ("_part" not in u, u))
@@ -52,6 +52,11 @@ def build(verbose=False, jobs=None):
     host_tmp = HOSTLIB + ".tmp"
     with ThreadPoolExecutor(jobs) as ex:
         futs = [ex.submit(_run, [HIPCC, *HIP_FLAGS, "-c", u, "-o", o], verbose) for u, o in zip(units, objs)]
+        # host-only parts of the library (LHE files)
+        lhe_obj = os.path.join(OBJ, "mgrw_lhe.o")
+        futs.append(ex.submit(_run, ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"),
+                                     "-c", os.path.join(CSRC, "mgrw_lhe.cpp"), "-o", lhe_obj], verbose))
+        objs = objs + [lhe_obj]
         # host validation build (tests only), compiled alongside
         futs.append(ex.submit(_run, ["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-I", CSRC, "-o", host_tmp,
                                      os.path.join(CSRC, "host_check.cpp")], verbose))

@@ -181,8 +181,8 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
             return fail(MGRW_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(err));
         return MGRW_OK;
     }
-    const int64_t blocks = (n + kBlock - 1) / kBlock;
-    if (blocks > 0x7fffffffLL) return fail(MGRW_ERR_ARG, "n_events too large for one launch");
+    // the widest grid: one event per wave, four waves per workgroup
+    if ((n + 3) / 4 > 0x7fffffffLL) return fail(MGRW_ERR_ARG, "n_events too large for one launch");
     qcd_launch a;
     std::memset(&a, 0, sizeof a);
     for (int k = 0; k < npts; ++k) a.pts[k] = qcd_point_of(pts[k]);

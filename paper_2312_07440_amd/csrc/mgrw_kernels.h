@@ -92,22 +92,37 @@ __device__ __forceinline__ void run_points(const KN& k, const BS& b, const qcd_l
     }
 }
 
+// Lanes per workgroup of the one-event-per-lane kernel: in single precision
+// each lane owns an LDS slot for its kinematics and bases, so large processes
+// use smaller workgroups to stay within the 160 KiB of LDS.
+template <class Proc, typename T>
+constexpr int lane_block() {
+    if constexpr (sizeof(T) == 4) {
+        constexpr size_t slot = sizeof(lds_slot<typename Proc::template kin<T>>) +
+                                sizeof(lds_slot<typename Proc::template basis<T>>);
+        return slot * 256 <= 160 * 1024 ? 256 : (slot * 128 <= 160 * 1024 ? 128 : 64);
+    } else {
+        return kBlock;
+    }
+}
+
 // One event per lane.  In single precision the per-lane kinematics and
 // wavefunction bases live in LDS (each lane owns a slot; no barriers); in
 // double precision they stay in registers.
 template <class Proc, typename T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__((lane_block<Proc, T>()))
 qcd_kernel(const double* __restrict__ mom, const double* __restrict__ w_in, int64_t n, qcd_launch a,
            double* __restrict__ out, double* __restrict__ me0_out) {
-    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    constexpr int NB = lane_block<Proc, T>();
+    const int64_t e = int64_t(blockIdx.x) * NB + threadIdx.x;
     if (e >= n) return;   // no barriers below: early exit is safe
     double p[Proc::NEXT][4];
     load_event<Proc::NEXT>(mom, n, e, p);
     using KinT = typename Proc::template kin<T>;
     using BasT = typename Proc::template basis<T>;
     if constexpr (sizeof(T) == 4) {
-        __shared__ lds_slot<KinT> ks[kBlock];
-        __shared__ lds_slot<BasT> bs[kBlock];
+        __shared__ lds_slot<KinT> ks[NB];
+        __shared__ lds_slot<BasT> bs[NB];
         KinT& k = ks[threadIdx.x].v;
         BasT& b = bs[threadIdx.x].v;
         Proc::kinematics(p, a.mt, k);
@@ -571,12 +586,14 @@ hipError_t launch_main(int fp64, const double* mom, const double* w_in, int64_t 
     if (a.mapping == MGRW_MAP_EVENT_PER_WAVE)
         return fp64 ? launch_wave<Proc, double>(mom, w_in, n, a, out, me0, s)
                     : launch_wave<Proc, float>(mom, w_in, n, a, out, me0, s);
-    const unsigned blocks = unsigned((n + kBlock - 1) / kBlock);
+    constexpr int NBD = lane_block<Proc, double>(), NBF = lane_block<Proc, float>();
     mark(a.t0, s);
     if (fp64)
-        hipLaunchKernelGGL((qcd_kernel<Proc, double>), dim3(blocks), dim3(kBlock), 0, s, mom, w_in, n, a, out, me0);
+        hipLaunchKernelGGL((qcd_kernel<Proc, double>), dim3(unsigned((n + NBD - 1) / NBD)), dim3(NBD), 0, s, mom, w_in,
+                           n, a, out, me0);
     else
-        hipLaunchKernelGGL((qcd_kernel<Proc, float>), dim3(blocks), dim3(kBlock), 0, s, mom, w_in, n, a, out, me0);
+        hipLaunchKernelGGL((qcd_kernel<Proc, float>), dim3(unsigned((n + NBF - 1) / NBF)), dim3(NBF), 0, s, mom, w_in,
+                           n, a, out, me0);
     mark(a.t1, s);
     return hipGetLastError();
 }
