@@ -157,6 +157,11 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
  * mixed-precision handles of those processes, 0 (off) otherwise; 0..1000000.
  * Applies to mgrw_eval_me, mgrw_reweight and mgrw_reweight_kpoly.
  *
+ * MGRW_OPT_COLOUR_MFMA (0 or 1; g g -> t tbar g g g): 1 forms the colour sum
+ * J^+ CF J on the matrix cores (bfloat16-split operands, float32
+ * accumulation; results agree with the default VALU form to float32
+ * rounding) after the last program part; default 0.
+ *
  * MGRW_OPT_KERNEL_TIMING (0 or 1): when 1, every launch records a pair of HIP
  * events on its stream around its amplitude kernel(s) (after the setup of
  * the kinematics, before the FP64 re-evaluation), read by
@@ -165,7 +170,7 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
  * Errors: MGRW_ERR_ARG (unknown option or value), MGRW_ERR_UNSUPPORTED
  * (mapping or rescue not available for the process or precision),
  * MGRW_ERR_DEVICE (event creation failed). */
-enum { MGRW_OPT_LANE_MAPPING = 1, MGRW_OPT_RESCUE_PPM = 2, MGRW_OPT_KERNEL_TIMING = 3 };
+enum { MGRW_OPT_LANE_MAPPING = 1, MGRW_OPT_RESCUE_PPM = 2, MGRW_OPT_KERNEL_TIMING = 3, MGRW_OPT_COLOUR_MFMA = 4 };
 enum { MGRW_MAP_AUTO = 0, MGRW_MAP_EVENT_PER_LANE = 1, MGRW_MAP_EVENT_PER_WAVE = 2 };
 mgrw_status mgrw_set_option(mgrw_process *p, int option, int64_t value);
 

@@ -194,6 +194,10 @@ class Process:
         v = {"auto": 0, "event_per_lane": 1, "event_per_wave": 2}[mapping]
         check(lib().mgrw_set_option(self._h, 1, v))
 
+    def set_colour_mfma(self, on=True):
+        """g g -> t tbar g g g: colour sum on the matrix cores (default off)."""
+        check(lib().mgrw_set_option(self._h, 4, 1 if on else 0))
+
     def set_kernel_timing(self, on=True):
         """Record HIP events around the amplitude kernel(s) of every launch."""
         check(lib().mgrw_set_option(self._h, 3, 1 if on else 0))

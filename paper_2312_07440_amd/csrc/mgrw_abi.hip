@@ -195,6 +195,7 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
                 : (info_of(p->proc).n_hel % 64 == 0 ? MGRW_MAP_EVENT_PER_WAVE : MGRW_MAP_EVENT_PER_LANE);
     a.kpoly = kpoly;
     a.rescue_tau = p->rescue_tau;
+    a.colour_mfma = p->colour_mfma;
     a.t0 = p->t0;
     a.t1 = p->t1;
     p->timed = p->t0 != nullptr;
@@ -236,6 +237,7 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     p->sur = nullptr;
     p->t0 = p->t1 = nullptr;
     p->timed = 0;
+    p->colour_mfma = 0;
     *out = p;
     return MGRW_OK;
 }
@@ -305,6 +307,13 @@ mgrw_status mgrw_set_option(mgrw_process* p, int option, int64_t value) {
         if (value != 0 && (p->prec != MGRW_MIXED || p->proc < MGRW_GG_TT || p->proc > MGRW_GG_TTGG))
             return fail(MGRW_ERR_UNSUPPORTED, "FP64 rescue: mixed precision g g -> t tbar + 0..2 g only");
         p->rescue_tau = double(value) * 1e-6;
+        return MGRW_OK;
+    }
+    if (option == MGRW_OPT_COLOUR_MFMA) {
+        if (value != 0 && value != 1) return fail(MGRW_ERR_ARG, "matrix-core colour sum: 0 or 1");
+        if (value == 1 && p->proc != MGRW_GG_TTGGG)
+            return fail(MGRW_ERR_UNSUPPORTED, "matrix-core colour sum: g g -> t tbar g g g only");
+        p->colour_mfma = int(value);
         return MGRW_OK;
     }
     if (option == MGRW_OPT_KERNEL_TIMING) {

@@ -24,4 +24,5 @@ struct mgrw_process {
     mgrw::surrogate* sur;               // null until trained or loaded
     hipEvent_t t0, t1;                  // amplitude-kernel timestamps (timing option), else null
     int timed;                          // a launch has recorded t0/t1
+    int colour_mfma;                    // g g -> t tbar g g g: colour sum on the matrix cores
 };

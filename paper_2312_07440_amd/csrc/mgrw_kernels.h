@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/mgrw.h"
 #include "mgrw_event.h"
@@ -25,6 +26,7 @@ struct qcd_launch {
     int kpoly;       // 1: kappa-polynomial evaluation (one program per helicity for all points)
     double rescue_tau;   // > 0: events with a gluon invariant |2 p_i.p_j|/s below it are redone in FP64
     hipEvent_t t0, t1;   // non-null: recorded around the amplitude kernel(s) of the launch
+    int colour_mfma;     // split programs: colour sum on the matrix cores (after the last part)
 };
 
 struct ew_launch {
@@ -489,16 +491,25 @@ hipError_t launch_kpoly(const double* mom, const double* w_in, int64_t n, const 
 // point and helicity of a batch of events, one event per wave with the
 // helicity configurations on the lanes.  The colour-flow amplitudes J travel
 // between the parts through HBM in a [event][point][component][helicity]
-// layout (consecutive lanes touch consecutive words); the last part forms the
-// colour sum, the helicity sum (wave reduction) and the reweighted weights.
+// layout (consecutive lanes touch consecutive words).  By default the last
+// part forms the colour sum (VALU), the helicity sum (wave reduction) and the
+// reweighted weights; with the matrix-core colour sum selected it stores J
+// too, and qcd_colour_mfma_kernel contracts J with the colour matrix.
 
-template <class Proc, typename T, int C>
+// Processes whose generated struct provides the bfloat16 split of the colour
+// matrix (MFMA_COLOUR) take the matrix-core colour sum.
+template <class P, class = void>
+struct mfma_colour : std::false_type {};
+template <class P>
+struct mfma_colour<P, std::void_t<decltype(P::MFMA_COLOUR)>> : std::bool_constant<P::MFMA_COLOUR> {};
+
+template <class Proc, typename T, int C, bool STORE_LAST>
 __global__ void __launch_bounds__(kBlock, 1)
 qcd_part_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t nb, T* __restrict__ jbuf,
                 const double* __restrict__ w_in, int64_t n, qcd_launch a, double* __restrict__ out,
                 double* __restrict__ me0_out) {
     constexpr int NH = Proc::NHEL, K2 = 2 * Proc::K;
-    constexpr bool LAST = C + 1 == Proc::NCHUNK;
+    constexpr bool LAST = C + 1 == Proc::NCHUNK && !STORE_LAST;   // finishes the events here
     static_assert(NH % 64 == 0, "helicity configurations must fill whole waves");
     const int64_t el = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (el >= nb) return;   // whole wave; no barriers below
@@ -558,9 +569,147 @@ qcd_part_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
 template <class Proc, typename T, int C>
 hipError_t launch_part(const event_data<Proc, T>* ev, int64_t e0, int64_t nb, T* jbuf, const double* w_in,
                        int64_t n, const qcd_launch& a, double* out, double* me0, hipStream_t s) {
-    hipLaunchKernelGGL((qcd_part_kernel<Proc, T, C>), dim3(unsigned((nb + kBlock / 64 - 1) / (kBlock / 64))),
-                       dim3(kBlock), 0, s, ev, e0, nb, jbuf, w_in, n, a, out, me0);
+    const dim3 grid(unsigned((nb + kBlock / 64 - 1) / (kBlock / 64)));
+    if constexpr (C + 1 == Proc::NCHUNK && mfma_colour<Proc>::value) {
+        if (a.colour_mfma) {
+            hipLaunchKernelGGL((qcd_part_kernel<Proc, T, C, true>), grid, dim3(kBlock), 0, s, ev, e0, nb, jbuf, w_in, n,
+                               a, out, me0);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((qcd_part_kernel<Proc, T, C, false>), grid, dim3(kBlock), 0, s, ev, e0, nb, jbuf, w_in, n, a,
+                       out, me0);
     return hipGetLastError();
+}
+
+// ---------------------------------------------- colour sum on the matrix cores
+//
+// After the last program part, J of every (event, point, helicity) is in HBM
+// as X[c][n] (c = 2 flow + re/im, n = helicity).  Per event and point the
+// colour sum over all helicities is
+//   sum_h J_h^+ CF J_h = sum_{f, n} X_f[n] (CF X)_f[n],
+// with X_f the 2 NHEL real columns (real and imaginary parts) of flow f.
+// D = CF X runs on v_mfma_f32_32x32x16_bf16: CF's integer numerators are the
+// exact sum of two bfloat16 matrices (CF_BF16_HI + CF_BF16_LO, padded to KP),
+// X is split into three bfloat16 terms x1 + x2 + x3 (24 significant bits), and
+// the five products with weight above 2^-24 are accumulated in float32; the
+// final dot product uses X itself (float32) from HBM.  One workgroup (4 waves)
+// per event; each wave owns a quarter of D's columns.
+
+typedef __attribute__((ext_vector_type(8))) __bf16 cbf16x8;
+typedef __attribute__((ext_vector_type(8))) unsigned short cu16x8;
+typedef __attribute__((ext_vector_type(16))) float cf32x16;
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<unsigned short>(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as_float(unsigned(b) << 16); }
+
+template <class Proc>
+__global__ void __launch_bounds__(kBlock)
+qcd_colour_mfma_kernel(const float* __restrict__ jbuf, int64_t e0, int64_t nb, const double* __restrict__ w_in,
+                       int64_t n, qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
+    constexpr int K = Proc::K, KP = Proc::KP, NH = Proc::NHEL, NCOL = 2 * NH;
+    static_assert(KP % 32 == 0 && NCOL % 128 == 0, "tile shapes");
+    constexpr int MT = KP / 32, KS = KP / 16, NT_WAVE = NCOL / 32 / (kBlock / 64);
+    const int64_t el = blockIdx.x;
+    if (el >= nb) return;   // whole block
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 31, lh = lane >> 5;
+    __shared__ double part[kBlock / 64];
+    const double w = (a.mode == 0 && w_in) ? w_in[e0 + el] : 1.0;
+    double me0 = 0.0;
+#pragma unroll 1
+    for (int kp = 0; kp < a.npts; ++kp) {
+        const float* X = jbuf + (el * a.npts + kp) * int64_t(2 * K) * NH;
+        float s = 0.0f;
+#pragma unroll 1
+        for (int t = 0; t < NT_WAVE; ++t) {
+            const int ncol = (wv * NT_WAVE + t) * 32 + lr;   // this lane's column of D
+            const int re_im = ncol / NH, h = ncol % NH;
+            // B = X in three bfloat16 terms, all k-steps of this column tile
+            cbf16x8 b1[KS], b2[KS], b3[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                cu16x8 u1, u2, u3;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int f = ks * 16 + lh * 8 + r;
+                    const float x = f < K ? X[int64_t(2 * f + re_im) * NH + h] : 0.0f;
+                    const unsigned short x1 = bf16_rne(x);
+                    const float r1 = x - bf16_float(x1);
+                    const unsigned short x2 = bf16_rne(r1);
+                    const unsigned short x3 = bf16_rne(r1 - bf16_float(x2));
+                    u1[r] = x1;
+                    u2[r] = x2;
+                    u3[r] = x3;
+                }
+                b1[ks] = __builtin_bit_cast(cbf16x8, u1);
+                b2[ks] = __builtin_bit_cast(cbf16x8, u2);
+                b3[ks] = __builtin_bit_cast(cbf16x8, u3);
+            }
+#pragma unroll 1
+            for (int mt = 0; mt < MT; ++mt) {
+                cf32x16 acc = {};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    cu16x8 hi, lo;
+                    const int row = mt * 32 + lr, k0 = ks * 16 + lh * 8;
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) {
+                        hi[r] = Proc::CF_BF16_HI[row * KP + k0 + r];
+                        lo[r] = Proc::CF_BF16_LO[row * KP + k0 + r];
+                    }
+                    const cbf16x8 ah = __builtin_bit_cast(cbf16x8, hi), al = __builtin_bit_cast(cbf16x8, lo);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b1[ks], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b2[ks], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b1[ks], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b3[ks], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b2[ks], acc, 0, 0, 0);
+                }
+                // D[m][ncol] for m = mt*32 + (r/4)*8 + lh*4 + r%4, dotted with X[m][ncol]
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int f = mt * 32 + (r / 4) * 8 + lh * 4 + r % 4;
+                    if (f < K) s += X[int64_t(2 * f + re_im) * NH + h] * acc[r];
+                }
+            }
+        }
+        double v = wave_sum(double(s));
+        if (lane == 0) part[wv] = v;
+        __syncthreads();
+        double me = 0.0;
+        for (int i = 0; i < kBlock / 64; ++i) me += part[i];
+        me *= Proc::NORM;
+        __syncthreads();   // part[] is rewritten for the next point
+        if (threadIdx.x == 0) {
+            const int64_t e = e0 + el;
+            if (kp == 0) {
+                me0 = me;
+                if (a.mode == 1)
+                    out[e] = me;
+                else if (me0_out)
+                    me0_out[e] = me;
+            } else {
+                out[int64_t(kp - 1) * n + e] = reweighted(w, me, me0);
+            }
+        }
+    }
+}
+
+template <class Proc>
+hipError_t launch_colour_mfma(const float* jbuf, int64_t e0, int64_t nb, const double* w_in, int64_t n,
+                              const qcd_launch& a, double* out, double* me0, hipStream_t s) {
+    if constexpr (mfma_colour<Proc>::value) {
+        if (!a.colour_mfma) return hipSuccess;
+        hipLaunchKernelGGL((qcd_colour_mfma_kernel<Proc>), dim3(unsigned(nb)), dim3(kBlock), 0, s, jbuf, e0, nb, w_in,
+                           n, a, out, me0);
+        return hipGetLastError();
+    } else {
+        return hipSuccess;
+    }
 }
 
 // Events per batch of the split programs (bounds the HBM buffer for J).

@@ -53,9 +53,11 @@ def generate(outdir=None, procs=None, force=False):
             calls = "\n".join(
                 f"        if (err == hipSuccess) err = launch_{name}_part{c}(ev, e0, nb, jbuf, w_in, n, a, out, me0, s);"
                 for c in range(nch))
+            calls += (f"\n        if (err == hipSuccess) err = launch_colour_mfma<{name}>(jbuf, e0, nb, w_in, n, a, out, "
+                      "me0, s);")
             body = (decls +
                     f"// Single precision only: kinematics for all events, then batches of\n"
-                    f"// kPartBatch events through the {nch} program parts.\n"
+                    f"// kPartBatch events through the {nch} program parts and the colour sum.\n"
                     f"hipError_t launch_{name}{sig} {{\n"
                     "    if (fp64) return hipErrorInvalidValue;\n"
                     f"    using ED = event_data<{name}, float>;\n"

@@ -518,6 +518,36 @@ def split_groups(ng, chunks):
     return [p for p in parts if p]
 
 
+def bf16_bits(x):
+    """bfloat16 bit pattern of x (round to nearest even), from its float32 bits."""
+    import struct
+    u = struct.unpack("<I", struct.pack("<f", x))[0]
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u & 0xFFFF
+
+
+def bf16_value(b):
+    import struct
+    return struct.unpack("<f", struct.pack("<I", b << 16))[0]
+
+
+def bf16_split_table(num, kp):
+    """Integer matrix num (K x K) padded with zeros to kp x kp, as two
+    bfloat16 matrices hi + lo that sum to it exactly (row-major bit patterns)."""
+    K = len(num)
+    hi, lo = [], []
+    for r in range(kp):
+        for c in range(kp):
+            v = num[r][c] if r < K and c < K else 0
+            h = bf16_bits(float(v))
+            rest = v - bf16_value(h)
+            l = bf16_bits(float(rest))
+            assert bf16_value(h) + bf16_value(l) == v, (v, h, l)
+            hi.append(h)
+            lo.append(l)
+    return hi, lo
+
+
 def emit_process(name, ng, chunks=1):
     """C++ source of the process struct for g g -> t tbar + (ng-2) g.
 
@@ -723,6 +753,21 @@ def emit_process(name, ng, chunks=1):
     for row in num:
         w("    {" + ", ".join(str(x) for x in row) + "},")
     w("  };")
+    if chunks > 1:
+        # colour matrix for the matrix cores: numerators padded to a multiple of
+        # 32 and split exactly into two bfloat16 terms (bit patterns)
+        kp = (K + 31) // 32 * 32
+        hi, lo = bf16_split_table(num, kp)
+        w("  static constexpr bool MFMA_COLOUR = true;")
+        w(f"  static constexpr int KP = {kp};")
+        w("  static constexpr unsigned short CF_BF16_HI[KP * KP] = {")
+        for r in range(kp):
+            w("    " + ", ".join(str(x) for x in hi[r * kp:(r + 1) * kp]) + ",")
+        w("  };")
+        w("  static constexpr unsigned short CF_BF16_LO[KP * KP] = {")
+        for r in range(kp):
+            w("    " + ", ".join(str(x) for x in lo[r * kp:(r + 1) * kp]) + ",")
+        w("  };")
     w("};")
     w("}  // namespace mgrw")
     return "\n".join(out) + "\n", em

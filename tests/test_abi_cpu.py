@@ -83,3 +83,10 @@ def test_photon_process_info_and_option_errors(L):
         p.set_params([{"alpha": -1.0}])
     with pytest.raises(bd.MgrwError):
         p.kernel_time_ms()                      # timing is off
+
+
+def test_colour_mfma_option_only_for_the_split_process(L):
+    with pytest.raises(bd.MgrwError, match="matrix-core"):
+        bd.Process("gg_ttgg", "mixed").set_colour_mfma(True)
+    bd.Process("gg_ttggg", "mixed").set_colour_mfma(True)
+    bd.Process("gg_ttgg", "mixed").set_colour_mfma(False)

@@ -147,3 +147,23 @@ def test_host_photon_recursion_matches_oracle():
     assert lib.mgrw_host_ee5a_me(_dp(mom), ctypes.c_int64(n), _dp(al), len(al), _dp(me)) == 0
     ref = oracle.ee_photons_me(mom, al)
     assert np.max(np.abs(me / ref - 1)) < 1e-12
+
+
+def test_colour_matrix_bf16_split_is_exact():
+    """The matrix-core colour sum of g g -> t tbar g g g uses the integer colour
+    numerators as the sum of two bfloat16 matrices; the split must be exact
+    and the padding zero."""
+    from fractions import Fraction
+    cf = P.colour_matrix_loops(5)
+    den = 1
+    for row in cf:
+        for x in row:
+            den = den * x.denominator // np.gcd(den, x.denominator)
+    num = [[int(x * den) for x in row] for row in cf]
+    hi, lo = P.bf16_split_table(num, 128)
+    for r in (0, 7, 119, 120, 127):
+        for c in (0, 5, 119, 120, 127):
+            v = num[r][c] if r < 120 and c < 120 else 0
+            assert P.bf16_value(hi[r * 128 + c]) + P.bf16_value(lo[r * 128 + c]) == v
+    assert max(abs(x) for row in num for x in row) < 1 << 16
+    assert Fraction(num[0][0], den) == cf[0][0]

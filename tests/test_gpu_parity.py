@@ -354,3 +354,33 @@ def test_kernel_timing(torch_dev):
     p.set_kernel_timing(False)
     with pytest.raises(RuntimeError):
         p.kernel_time_ms()
+
+
+@pytest.mark.parametrize("n", [70, 8229])
+def test_gg_ttggg_matrix_core_colour_sum(torch_dev, n):
+    """The colour sum of g g -> t tbar g g g on the matrix cores (bfloat16-split
+    operands, float32 accumulation) against the VALU colour sum and, for the
+    small case, the oracle."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    say(f"case gg_ttggg matrix-core colour sum n={n}")
+    mom = generate_events("gg_ttggg", n, first_event=555)
+    kap = kappa_points(4)
+    outs = []
+    for mf in (True, False):
+        p = mg.Process("gg_ttggg", "mixed")
+        p.set_params([{"kappa_ttg": float(k)} for k in kap])
+        if mf:
+            p.set_colour_mfma(True)
+        me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        out = p.reweight(to_dev(torch, mom), me_base_out=me0)
+        torch.cuda.synchronize()
+        outs.append((out.cpu().numpy(), me0.cpu().numpy()))
+    e = relerr(outs[0][0], outs[1][0]).max()
+    e0 = relerr(outs[0][1], outs[1][1]).max()
+    say(f"  matrix cores vs VALU: |M|^2 {e0:.3e}, W' {e:.3e}")
+    assert e <= 1e-5 and e0 <= 1e-5
+    if n <= 100:
+        me_ref, w_ref = oracle_qcd("gg_ttggg", mom, kap, np.ones(n))
+        assert relerr(outs[0][1], me_ref[0]).max() <= TOL["mixed"]
+        assert relerr(outs[0][0], w_ref).max() <= TOL["mixed"]
