@@ -68,10 +68,10 @@ constexpr int kpoly_pairs() {
 }
 
 // Add one helicity configuration's B_ab (pair (a <= b) at b(b+1)/2 + a).
-template <class Proc, typename T, typename KN, typename BS>
-MGRW_HD void kpoly_helicity(const KN& k, const BS& b, int h, double* B) {
+// w: storage for the external wavefunctions (registers or an LDS slot).
+template <class Proc, typename T, typename KN, typename BS, typename EXT>
+MGRW_HD void kpoly_helicity(const KN& k, const BS& b, int h, double* B, EXT& w) {
     typename Proc::template coup<T> c = {T(1), T(1), T(1)};
-    typename Proc::template ext<T> w;
     Proc::template external<T>(b, h, w);
     cx<T> J[Proc::NG * Proc::K];
     Proc::amplitude_kpoly(w, k, c, J);
@@ -91,6 +91,12 @@ MGRW_HD void kpoly_helicity(const KN& k, const BS& b, int h, double* B) {
         for (int pa = 0; pa <= pb; ++pa)
             B[pb * (pb + 1) / 2 + pa] += double(Proc::template re_dot<TA, T>(J + pa * Proc::K, Z));
     }
+}
+
+template <class Proc, typename T, typename KN, typename BS>
+MGRW_HD void kpoly_helicity(const KN& k, const BS& b, int h, double* B) {
+    typename Proc::template ext<T> w;
+    kpoly_helicity<Proc, T>(k, b, h, B, w);
 }
 
 // |M|^2 at couplings (gs, kappa) from the helicity-summed B.

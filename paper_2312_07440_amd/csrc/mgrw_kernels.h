@@ -226,7 +226,11 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* __rest
 #pragma unroll 1
         for (int hc = 0; hc < Proc::NHEL; hc += 64) {
             __asm__ volatile("" ::: "memory");
-            typename Proc::template ext<T> wf;
+            // the lane's external wavefunctions live in its own LDS slot: they
+            // are read throughout the program, and in registers they push the
+            // program's working set into scratch
+            __shared__ lds_slot<typename Proc::template ext<T>> wfs[kBlock];
+            typename Proc::template ext<T>& wf = wfs[threadIdx.x].v;
             Proc::template external<T>(b, hc + lane, wf);
             cx<T> J[Proc::K];
             Proc::amplitude(wf, k, c, J);
