@@ -343,6 +343,7 @@ qcd_rescue_kernel(const double* __restrict__ mom, const int64_t* __restrict__ li
                   const unsigned long long* __restrict__ count, const double* __restrict__ w_in, int64_t n,
                   qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
     __shared__ event_data<Proc, double> sh[kBlock / 64];
+    __shared__ lds_slot<typename Proc::template ext<double>> wfs[kBlock];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t cnt = int64_t(count[0]);
@@ -379,7 +380,7 @@ qcd_rescue_kernel(const double* __restrict__ mom, const int64_t* __restrict__ li
 #pragma unroll 1
                 for (int hc = 0; hc < Proc::NHEL; hc += 64) {
                     if (hc + lane < Proc::NHEL) {
-                        typename Proc::template ext<double> wf;
+                        typename Proc::template ext<double>& wf = wfs[threadIdx.x].v;   // own slot
                         Proc::template external<double>(d.b, hc + lane, wf);
                         cx<double> J[Proc::K];
                         Proc::amplitude(wf, d.k, c, J);
@@ -531,7 +532,8 @@ qcd_part_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
 #pragma unroll 1
         for (int hc = 0; hc < NH; hc += 64) {
             __asm__ volatile("" ::: "memory");
-            typename Proc::template ext<T> wf;
+            __shared__ lds_slot<typename Proc::template ext<T>> wfs[kBlock];
+            typename Proc::template ext<T>& wf = wfs[threadIdx.x].v;   // own slot, as in qcd_wave_kernel
             Proc::template external<T>(b, hc + lane, wf);
             T* jp = jbuf + (el * a.npts + kp) * int64_t(K2) * NH + hc + lane;
             cx<T> J[Proc::K];
