@@ -90,3 +90,12 @@ def test_colour_mfma_option_only_for_the_split_process(L):
         bd.Process("gg_ttgg", "mixed").set_colour_mfma(True)
     bd.Process("gg_ttggg", "mixed").set_colour_mfma(True)
     bd.Process("gg_ttgg", "mixed").set_colour_mfma(False)
+
+
+def test_unsupported_precisions_and_processes(L):
+    h = ctypes.c_void_p()
+    base = bd.make_params()
+    assert L.mgrw_create_process(bd.GG_TTGGG, bd.FP64, ctypes.byref(base), ctypes.byref(h)) == bd.ERR_UNSUPPORTED
+    assert L.mgrw_create_process(bd.EE_5A + 1, bd.FP64, ctypes.byref(base), ctypes.byref(h)) == bd.ERR_ARG
+    assert L.mgrw_create_process(bd.EE_5A, bd.FP64, ctypes.byref(base), ctypes.byref(h)) == bd.OK
+    L.mgrw_destroy_process(h)

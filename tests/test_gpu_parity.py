@@ -384,3 +384,25 @@ def test_gg_ttggg_matrix_core_colour_sum(torch_dev, n):
         me_ref, w_ref = oracle_qcd("gg_ttggg", mom, kap, np.ones(n))
         assert relerr(outs[0][1], me_ref[0]).max() <= TOL["mixed"]
         assert relerr(outs[0][0], w_ref).max() <= TOL["mixed"]
+
+
+def test_maximum_points_and_varied_couplings(torch_dev):
+    """64 new points (the maximum) that vary alpha_s as well as kappa, with input
+    weights of both signs and zeros, g g -> t tbar g g (mixed, event per wave)."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 65
+    say(f"case 64 points, varied alpha_s, gg_ttgg n={n}")
+    mom = generate_events("gg_ttgg", n, first_event=31337)
+    w = np.random.default_rng(8).normal(size=n)
+    w[::7] = 0.0
+    kap = kappa_points(64)
+    als = np.linspace(0.09, 0.14, 64)
+    p = mg.Process("gg_ttgg", "mixed")
+    p.set_params([{"alphas": float(a), "kappa_ttg": float(k)} for a, k in zip(als, kap)])
+    out = p.reweight(to_dev(torch, mom), w_in=to_dev(torch, w)).cpu().numpy()
+    me = oracle.qcd_me(4, mom, [(ALS, MT, 1.0)] + [(float(a), MT, float(k)) for a, k in zip(als, kap)])
+    ref = oracle.reweight(me, w)
+    nz = w != 0
+    assert np.all(out[:, ~nz] == 0)
+    assert relerr(out[:, nz], ref[:, nz]).max() <= TOL["mixed"]
