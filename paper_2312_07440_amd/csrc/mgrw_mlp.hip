@@ -269,6 +269,10 @@ __global__ void reduce_parts(const float* __restrict__ part, int nparts, int64_t
     out[i] = s;
 }
 
+// Row chunks of the bias-gradient column sums: enough workgroups to spread
+// over the 256 CUs, few enough for one pass of the final reduction.
+constexpr int kBiasChunks = 256;
+
 // Partial column sums of a bfloat16 [m][H] matrix (bias gradients): block b
 // sums rows [b*rows_per, (b+1)*rows_per) of every column; deterministic.
 __global__ void colsum_bf16(const uint16_t* __restrict__ g, int64_t m, int64_t rows_per, float* __restrict__ part) {
@@ -434,9 +438,9 @@ hipError_t ensure_rows(surrogate* s, int64_t rows) {
     if ((e = s->y.alloc(rows)) != hipSuccess) return e;
     if ((e = s->pred.alloc(rows)) != hipSuccess) return e;
     // split-K partials (<= 16 slices of H x H), output-layer block partials,
-    // and bias-gradient partials (<= 64 row chunks)
+    // and bias-gradient partials (<= kBiasChunks row chunks)
     if ((e = s->part.alloc(std::max<size_t>(size_t(16) * H * H, size_t(rows / 64 + 1) * (H + 1)) +
-                           size_t(64) * H)) != hipSuccess)
+                           size_t(kBiasChunks) * H)) != hipSuccess)
         return e;
     s->rows_cap = rows;
     return hipSuccess;
@@ -501,7 +505,7 @@ mgrw_status backward(surrogate* s, int64_t rows, hipStream_t st) {
     int cur = 0;
     int splits = 16;   // split-K slices: each a multiple of 32 rows
     while (splits > 1 && rows % (int64_t(32) * splits) != 0) --splits;
-    const int nchunk = int(std::min<int64_t>(64, rows));
+    const int nchunk = int(std::min<int64_t>(kBiasChunks, rows));
     const int64_t rows_per = (rows + nchunk - 1) / nchunk;
     float* bias_part = s->part.p + size_t(16) * H * H;
     for (int l = 3; l >= 0; --l) {
