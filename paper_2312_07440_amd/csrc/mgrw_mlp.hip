@@ -60,6 +60,19 @@ __device__ __forceinline__ float dsilu(float z) {
     return s * (1.0f + z * (1.0f - s));
 }
 
+// Counter-based uniform draws in (0, 1): SplitMix64 finaliser of
+// (seed, stream, index); the same on the host and the device.
+__host__ __device__ inline uint64_t smix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ inline double u01(uint64_t seed, uint64_t stream, uint64_t i) {
+    uint64_t h = smix(seed + 0x9E3779B97F4A7C15ull * (stream + 1));
+    h = smix(h + 0x9E3779B97F4A7C15ull * (i + 1));
+    return (double(h >> 11) + 0.5) * 0x1.0p-53;
+}
+
 // ------------------------------------------------------------------ GEMM
 //
 // C[m][n] = sum_k A(m, k) B(k, n), bfloat16 operands, float accumulation,
@@ -370,18 +383,144 @@ __global__ void audit_kernel(const int64_t* __restrict__ idx, int64_t na, const 
     for (int64_t a = threadIdx.x; a < na; a += 256) w_out[int64_t(k) * n + idx[a]] = w_exact[int64_t(k) * na + a];
 }
 
-// --------------------------------------------------------------- host side
+// ------------------------------------------------- fused inference
+//
+// All four hidden layers and the output unit for 128 feature rows per
+// workgroup: the rows' activations stay in LDS (two 128 x 256 bfloat16
+// buffers), each wave computes 128 rows x 64 units of a layer on
+// v_mfma_f32_32x32x16_bf16 with the weights read from the (L2-resident)
+// bfloat16 copy, and the epilogue (bias, SiLU, rounding to bfloat16) writes
+// the next layer's input.  Rows are event-major (r = e P + k): layer 1 reads
+// the event's features (computed once per event) and the point's kappa.
+// Same arithmetic as the layer-by-layer training kernels.
+constexpr int FR = 128;         // rows per workgroup
+constexpr int LDA = H + 8;      // LDS row stride (bfloat16)
 
-uint64_t smix(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
+__global__ void __launch_bounds__(256, 1)
+mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restrict__ kappa, int64_t rows, int64_t e0,
+                 int64_t n_events, const uint16_t* __restrict__ wbf, const float* __restrict__ par,
+                 const double* __restrict__ w_in, double* __restrict__ w_out) {
+    __shared__ uint16_t act[2][FR][LDA];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, lr = lane & 31, lh = lane >> 5;
+    const int64_t r0 = int64_t(blockIdx.x) * FR;
+    for (int i = t; i < FR * K0; i += 256) {
+        const int mrow = i / K0, c = i % K0;
+        const int64_t r = r0 + mrow;
+        uint16_t v = 0;
+        if (r < rows) {
+            const int k = int(r % P);
+            v = c == NRAW - 1 ? f2bf(float((kappa[k] - 1.0) / 0.2)) : xev[(r / P) * K0 + c];
+        }
+        act[0][mrow][c] = v;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int l = 0; l < 4; ++l) {
+        const int K = K_IN[l];
+        const uint16_t* W = wbf + W_OFF[l];   // [H][K]
+        const float* bias = par + B_OFF[l];
+        uint16_t (*in)[LDA] = act[l & 1];
+        uint16_t (*out)[LDA] = act[(l + 1) & 1];
+        f32x16 acc[4][2];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) acc[rt][0] = acc[rt][1] = f32x16{};
+#pragma unroll 4
+        for (int ks = 0; ks < K / 16; ++ks) {
+            bf16x8 b[2];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                b[ct] = *reinterpret_cast<const bf16x8*>(W + int64_t((wave * 2 + ct) * 32 + lr) * K + ks * 16 + lh * 8);
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&in[rt * 32 + lr][ks * 16 + lh * 8]);
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[ct], acc[rt][ct], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int n = (wave * 2 + ct) * 32 + lr;
+            const float bn = bias[n];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    out[rt * 32 + (r >> 2) * 8 + lh * 4 + (r & 3)][n] = f2bf(silu(acc[rt][ct][r] + bn));
+        }
+        __syncthreads();
+    }
+    // output unit: act[0] holds the last hidden layer; two threads per row
+    const int mrow = t >> 1, half = t & 1;
+    float h = 0.0f;
+    const float* w5 = par + OFF_W5 + half * (H / 2);
+    for (int j = 0; j < H / 2; ++j) h += bf2f(act[0][mrow][half * (H / 2) + j]) * w5[j];
+    h += __shfl_xor(h, 1);
+    const int64_t r = r0 + mrow;
+    if (half == 0 && r < rows) {
+        const int k = int(r % P);
+        const int64_t e = e0 + r / P;
+        const float yh = float(kappa[k] - 1.0) * (h + par[OFF_B5]);
+        const double w = w_in ? w_in[e] : 1.0;
+        w_out[int64_t(k) * n_events + e] = w * exp(double(yh));
+    }
 }
-double u01(uint64_t seed, uint64_t stream, uint64_t i) {
-    uint64_t h = smix(seed + 0x9E3779B97F4A7C15ull * (stream + 1));
-    h = smix(h + 0x9E3779B97F4A7C15ull * (i + 1));
-    return (double(h >> 11) + 0.5) * 0x1.0p-53;
+
+// Audit selection u01(seed, 2, e) < f, compacted in event order: per-block
+// counts, one-workgroup exclusive scan, then each block writes its events.
+__global__ void __launch_bounds__(256)
+audit_count_kernel(uint64_t seed, double f, int64_t n, unsigned* __restrict__ counts) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const bool sel = e < n && u01(seed, 2, uint64_t(e)) < f;
+    __shared__ unsigned c;
+    if (threadIdx.x == 0) c = 0;
+    __syncthreads();
+    if (sel) atomicAdd(&c, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) counts[blockIdx.x] = c;
 }
+
+__global__ void __launch_bounds__(256)
+audit_scan_kernel(const unsigned* __restrict__ counts, int64_t nb, int64_t* __restrict__ offsets) {
+    __shared__ int64_t tot[256];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 255) / 256, b0 = t * per, b1 = b0 + per < nb ? b0 + per : nb;
+    int64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += counts[b];
+    tot[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int64_t v = tot[i];
+            tot[i] = run;
+            run += v;
+        }
+        offsets[nb] = run;   // total
+    }
+    __syncthreads();
+    int64_t run = tot[t];
+    for (int64_t b = b0; b < b1; ++b) {
+        offsets[b] = run;
+        run += counts[b];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+audit_fill_kernel(uint64_t seed, double f, int64_t n, const int64_t* __restrict__ offsets, int64_t* __restrict__ idx) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const bool sel = e < n && u01(seed, 2, uint64_t(e)) < f;
+    __shared__ unsigned flags[256];
+    flags[threadIdx.x] = sel ? 1u : 0u;
+    __syncthreads();
+    if (sel) {
+        unsigned pos = 0;
+        for (unsigned i = 0; i < threadIdx.x; ++i) pos += flags[i];
+        idx[offsets[blockIdx.x] + pos] = e;
+    }
+}
+
+// --------------------------------------------------------------- host side
 
 template <typename T>
 struct dbuf {   // device buffer owned by the library
@@ -728,20 +867,17 @@ mgrw_status mgrw_reweight_surrogate(mgrw_process* p, const double* mom, const do
     r = upload_kappas(p, kap, st);
     if (r != MGRW_OK) return r;
 
-    // 1. surrogate weights for every (event, point), in chunks of events
+    // 1. surrogate weights for every (event, point), in chunks of events: the
+    // event features once per event, then the fused network over its P rows
     const int64_t chunk_ev = std::max<int64_t>(1, (int64_t(1) << 20) / P);
     HIPCHK(ensure_rows(s, ((chunk_ev * P + 63) / 64) * 64));
     for (int64_t e0 = 0; e0 < n_events; e0 += chunk_ev) {
         const int64_t ne = std::min(chunk_ev, n_events - e0);
-        const int64_t rows = ne * P, rows64 = ((rows + 63) / 64) * 64;
-        hipLaunchKernelGGL(features_kernel, dim3(unsigned((rows + 255) / 256)), dim3(256), 0, st, mom, n_ext,
-                           n_events, e0, P, kap.p, rows, s->x0.p, s->kd.p);
-        if (rows64 > rows)
-            HIPCHK(hipMemsetAsync(s->x0.p + rows * K0, 0, size_t(rows64 - rows) * K0 * sizeof(uint16_t), st));
-        forward(s, rows64, false, st);
-        hipLaunchKernelGGL((head_kernel<false>), dim3(unsigned(rows64 / 64)), dim3(256), 0, st, s->act[3].p,
-                           nullptr, s->par.p + OFF_W5, s->par.p + OFF_B5, s->kd.p, nullptr, rows, 0.0, nullptr,
-                           nullptr, nullptr, nullptr, P, n_events, e0, w_in, w_out);
+        const int64_t rows = ne * P;
+        hipLaunchKernelGGL(features_kernel, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, mom, n_ext,
+                           n_events, e0, 1, kap.p, ne, s->x0.p, s->kd.p);
+        hipLaunchKernelGGL(mlp_infer_kernel, dim3(unsigned((rows + FR - 1) / FR)), dim3(256), 0, st, s->x0.p, P,
+                           kap.p, rows, e0, n_events, s->pbf.p, s->par.p, w_in, w_out);
     }
     HIPCHK(hipGetLastError());
 
@@ -751,11 +887,19 @@ mgrw_status mgrw_reweight_surrogate(mgrw_process* p, const double* mom, const do
     HIPCHK(part.alloc(size_t(P) * sblocks + size_t(P) * 3));
     hipLaunchKernelGGL(sum_rows, dim3(sblocks, unsigned(P)), dim3(256), 0, st, w_out, P, n_events, part.p);
 
-    // 3. audit: events with u(seed, e) < fraction, evaluated exactly
-    std::vector<int64_t> idx;
-    for (int64_t e = 0; e < n_events; ++e)
-        if (u01(seed, 2, uint64_t(e)) < audit_fraction) idx.push_back(e);
-    const int64_t na = int64_t(idx.size());
+    // 3. audit: events with u(seed, e) < fraction, evaluated exactly (selected
+    // and compacted on the device; the count is read back)
+    const int64_t nblk = (n_events + 255) / 256;
+    dbuf<unsigned> acount;
+    dbuf<int64_t> aoff;
+    HIPCHK(acount.alloc(size_t(nblk)));
+    HIPCHK(aoff.alloc(size_t(nblk) + 1));
+    hipLaunchKernelGGL(audit_count_kernel, dim3(unsigned(nblk)), dim3(256), 0, st, uint64_t(seed), audit_fraction,
+                       n_events, acount.p);
+    hipLaunchKernelGGL(audit_scan_kernel, dim3(1), dim3(256), 0, st, acount.p, nblk, aoff.p);
+    int64_t na = 0;
+    HIPCHK(hipMemcpyAsync(&na, aoff.p + nblk, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     std::vector<double> stats(size_t(P) * 3, 0.0);
     if (na > 0) {
         dbuf<int64_t> didx;
@@ -764,7 +908,8 @@ mgrw_status mgrw_reweight_surrogate(mgrw_process* p, const double* mom, const do
         HIPCHK(mom_a.alloc(size_t(na) * n_ext * 4));
         HIPCHK(w_a.alloc(size_t(na)));
         HIPCHK(w_ex.alloc(size_t(na) * P));
-        HIPCHK(hipMemcpyAsync(didx.p, idx.data(), size_t(na) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(audit_fill_kernel, dim3(unsigned(nblk)), dim3(256), 0, st, uint64_t(seed), audit_fraction,
+                           n_events, aoff.p, didx.p);
         hipLaunchKernelGGL(gather_events, dim3(unsigned((na + 255) / 256)), dim3(256), 0, st, mom, n_ext, n_events,
                            didx.p, na, w_in, mom_a.p, w_a.p);
         r = mgrw_reweight(p, mom_a.p, w_a.p, na, w_ex.p, nullptr, stream);

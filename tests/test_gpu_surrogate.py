@@ -84,6 +84,62 @@ def test_fwd_bwd_parity(torch_dev):
         assert e_64 < 6e-2, name
 
 
+def test_inference_matches_oracle_network(torch_dev):
+    """Surrogate weights of the fused inference kernel (event features once per
+    event, all layers in LDS) against the oracle network on the oracle's
+    features, with bfloat16 rounding emulated; ragged row count (n P not a
+    multiple of the 128-row tile), every process size."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    params = mlp.init_params(9).astype(np.float32)
+    kap = kappa_points(8)
+    for proc, n in (("gg_ttgg", 1237), ("gg_tt", 301), ("gg_ttg", 517)):
+        say(f"case surrogate fused inference {proc} n={n} P={len(kap)}")
+        p = mg.Process(proc, "mixed")
+        p.set_params([{"kappa_ttg": float(k)} for k in kap])
+        p.set_surrogate_params(params)
+        mom_np = generate_events(proc, n, first_event=5 * 10 ** 5)
+        w = np.random.default_rng(4).uniform(0.5, 2.0, n)
+        out, _, fb = p.reweight_surrogate(dev(torch, mom_np), w_in=dev(torch, w), audit_fraction=1e-12, seed=5,
+                                          max_audit_error=1.0)
+        torch.cuda.synchronize()
+        assert not fb
+        yh = np.log(out.cpu().numpy() / w[None, :])            # [P, n]
+        x, kd = mlp.features(mom_np, kap)
+        ye, _ = mlp.forward(params.astype(np.float64), x, kd, emulate_bf16=True)
+        ye = ye.reshape(n, len(kap)).T
+        err = rel_l2(yh, ye)
+        say(f"  yhat rel-L2 vs bf16-emulating oracle {err:.2e}")
+        assert err < 1e-3
+        assert np.all(yh[np.isclose(kap, 1.0)] == 0.0)
+
+
+def test_audit_selection_is_the_counter_hash(torch_dev, trained_ttg):
+    """The device-side audit selection is exactly {e : u(seed, 2, e) < f} with
+    u the SplitMix64-finaliser draw, recomputed here in Python integers."""
+    torch = torch_dev
+    p, _ = trained_ttg
+    n, f, seed = 3000, 0.1, 123
+    say(f"case surrogate audit selection n={n} f={f}")
+    mom = dev(torch, generate_events("gg_ttg", n, first_event=7 * 10 ** 5))
+    pure, _, _ = p.reweight_surrogate(mom, audit_fraction=1e-12, seed=seed, max_audit_error=1.0)
+    out, st, _ = p.reweight_surrogate(mom, audit_fraction=f, seed=seed, max_audit_error=1.0)
+    torch.cuda.synchronize()
+    audited = np.all(out.cpu().numpy() != pure.cpu().numpy(), axis=0)
+    M = (1 << 64) - 1
+    G = 0x9E3779B97F4A7C15
+
+    def mix(z):
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    h0 = mix((seed + G * 3) & M)
+    expect = np.array([((mix((h0 + G * (e + 1)) & M) >> 11) + 0.5) * 2.0 ** -53 < f for e in range(n)])
+    assert np.array_equal(audited, expect)
+    assert int(st[0, 4]) == int(expect.sum())
+
+
 @pytest.fixture(scope="module")
 def trained_ttg(torch_dev):
     import paper_2312_07440_amd as mg
