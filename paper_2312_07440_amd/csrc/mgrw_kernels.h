@@ -303,7 +303,15 @@ qcd_kpoly_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* 
 #pragma unroll 1
     for (int hc = 0; hc < Proc::NHEL; hc += 64) {
         __asm__ volatile("" ::: "memory");
-        kpoly_helicity<Proc, T>(ev[e].k, ev[e].b, hc + lane, B);
+        if constexpr (sizeof(T) == 8) {
+            // double precision: external wavefunctions in the lane's own LDS
+            // slot, as in qcd_wave_kernel (10 % faster for g g -> t tbar g g;
+            // in single precision registers are faster)
+            __shared__ lds_slot<typename Proc::template ext<T>> wfs[kBlock];
+            kpoly_helicity<Proc, T>(ev[e].k, ev[e].b, hc + lane, B, wfs[threadIdx.x].v);
+        } else {
+            kpoly_helicity<Proc, T>(ev[e].k, ev[e].b, hc + lane, B);
+        }
     }
 #pragma unroll
     for (int i = 0; i < kpoly_pairs<Proc>(); ++i) B[i] = wave_sum(B[i]);

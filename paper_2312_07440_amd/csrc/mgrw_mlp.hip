@@ -282,6 +282,22 @@ __global__ void reduce_parts(const float* __restrict__ part, int nparts, int64_t
     out[i] = s;
 }
 
+// out[i] = sum over s of part[s][i] for many partials of a short row (bias
+// and output-layer gradients): one workgroup per column i, its 256 threads
+// taking partials s = t, t + 256, ..., then a fixed-order tree; deterministic.
+__global__ void __launch_bounds__(256)
+reduce_cols(const float* __restrict__ part, int nparts, int64_t len, float* __restrict__ out) {
+    const int t = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    float s = 0.0f;
+    for (int p = t; p < nparts; p += 256) s += part[int64_t(p) * len + i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    __shared__ float w[4];
+    if ((t & 63) == 0) w[t >> 6] = s;
+    __syncthreads();
+    if (t == 0) out[i] = (w[0] + w[1]) + (w[2] + w[3]);
+}
+
 // Row chunks of the bias-gradient column sums: enough workgroups to spread
 // over the 256 CUs, few enough for one pass of the final reduction.
 constexpr int kBiasChunks = 256;
@@ -659,7 +675,7 @@ mgrw_status backward(surrogate* s, int64_t rows, hipStream_t st) {
         hipLaunchKernelGGL(reduce_parts, dim3(unsigned((H * kin + 255) / 256)), dim3(256), 0, st, s->part.p, splits,
                            int64_t(H) * kin, s->grad.p + W_OFF[l]);
         hipLaunchKernelGGL(colsum_bf16, dim3(unsigned(nchunk)), dim3(H), 0, st, dzl, rows, rows_per, bias_part);
-        hipLaunchKernelGGL(reduce_parts, dim3(1), dim3(256), 0, st, bias_part, nchunk, int64_t(H),
+        hipLaunchKernelGGL(reduce_cols, dim3(H), dim3(256), 0, st, bias_part, nchunk, int64_t(H),
                            s->grad.p + B_OFF[l]);
         if (l > 0) {
             // da[m][k] = sum_n dz[m][n] W[n][k]: A = dz (n contiguous as k), B(n, k) = W[n*H + k]
@@ -682,7 +698,7 @@ mgrw_status head_train(surrogate* s, int64_t rows, double inv_m, hipStream_t st)
                        s->par.p + OFF_W5, s->par.p + OFF_B5, s->kd.p, s->y.p, rows, inv_m, s->pred.p, s->dz[0].p,
                        s->part.p, s->lossd.p, 0, int64_t(0), int64_t(0), nullptr, nullptr);
     // dw5 and db5 from the block partials (w5 and b5 are contiguous)
-    hipLaunchKernelGGL(reduce_parts, dim3(2), dim3(256), 0, st, s->part.p, int(blocks), int64_t(H + 1),
+    hipLaunchKernelGGL(reduce_cols, dim3(H + 1), dim3(256), 0, st, s->part.p, int(blocks), int64_t(H + 1),
                        s->grad.p + OFF_W5);
     HIPCHK(hipGetLastError());
     return MGRW_OK;
