@@ -401,33 +401,41 @@ __global__ void audit_kernel(const int64_t* __restrict__ idx, int64_t na, const 
 
 // ------------------------------------------------- fused inference
 //
-// All four hidden layers and the output unit for 128 feature rows per
-// workgroup: the rows' activations stay in LDS (two 128 x 256 bfloat16
-// buffers), each wave computes 128 rows x 64 units of a layer on
-// v_mfma_f32_32x32x16_bf16 with the weights read from the (L2-resident)
-// bfloat16 copy, and the epilogue (bias, SiLU, rounding to bfloat16) writes
-// the next layer's input.  Rows are event-major (r = e P + k): layer 1 reads
-// the event's features (computed once per event) and the point's kappa.
-// Same arithmetic as the layer-by-layer training kernels.
-constexpr int FR = 128;         // rows per workgroup
+// All four hidden layers and the output unit for 64 feature rows per
+// workgroup: the rows' activations stay in LDS (two 64 x 256 bfloat16
+// buffers, 67.6 KB, so two workgroups share a CU and one's epilogue overlaps
+// the other's matrix work).  Each wave computes 64 units x 64 rows of a layer
+// on v_mfma_f32_32x32x16_bf16 as D = W A^T: the weights (rows of the
+// L2-resident bfloat16 copy) are the first operand, the activations the
+// second, so that a lane's four consecutive accumulator rows are four
+// consecutive units of one feature row and the epilogue (bias, SiLU, rounding
+// to bfloat16) stores them as one 8-byte word.  Rows are event-major
+// (r = e P + k): layer 1 reads the event's features (computed once per event)
+// and the point's kappa.  Same arithmetic as the layer-by-layer training
+// kernels.  rows < 2^31.
+constexpr int FR = 64;          // rows per workgroup
 constexpr int LDA = H + 8;      // LDS row stride (bfloat16)
 
-__global__ void __launch_bounds__(256, 1)
-mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restrict__ kappa, int64_t rows, int64_t e0,
+__global__ void __launch_bounds__(256, 2)
+mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restrict__ kappa, int rows, int64_t e0,
                  int64_t n_events, const uint16_t* __restrict__ wbf, const float* __restrict__ par,
                  const double* __restrict__ w_in, double* __restrict__ w_out) {
-    __shared__ uint16_t act[2][FR][LDA];
+    __shared__ __align__(16) uint16_t act[2][FR][LDA];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63, lr = lane & 31, lh = lane >> 5;
-    const int64_t r0 = int64_t(blockIdx.x) * FR;
-    for (int i = t; i < FR * K0; i += 256) {
-        const int mrow = i / K0, c = i % K0;
-        const int64_t r = r0 + mrow;
-        uint16_t v = 0;
+    const int r0 = int(blockIdx.x) * FR;
+    {
+        // layer-1 input: 4 threads per row, 16 columns each
+        const int mrow = t >> 2, q = t & 3, r = r0 + mrow;
+        uint4 v0 = {0, 0, 0, 0}, v1 = {0, 0, 0, 0};
         if (r < rows) {
-            const int k = int(r % P);
-            v = c == NRAW - 1 ? f2bf(float((kappa[k] - 1.0) / 0.2)) : xev[(r / P) * K0 + c];
+            const uint4* src = reinterpret_cast<const uint4*>(xev + int64_t(r / P) * K0 + q * 16);
+            v0 = src[0];
+            v1 = src[1];
         }
-        act[0][mrow][c] = v;
+        uint4* dst = reinterpret_cast<uint4*>(&act[0][mrow][q * 16]);
+        dst[0] = v0;
+        dst[1] = v1;
+        if (q == 1 && r < rows) act[0][mrow][NRAW - 1] = f2bf(float((kappa[r % P] - 1.0) / 0.2));
     }
     __syncthreads();
 #pragma unroll 1
@@ -437,44 +445,60 @@ mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restri
         const float* bias = par + B_OFF[l];
         uint16_t (*in)[LDA] = act[l & 1];
         uint16_t (*out)[LDA] = act[(l + 1) & 1];
-        f32x16 acc[4][2];
+        f32x16 acc[2][2];   // [unit tile][row tile]
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) acc[rt][0] = acc[rt][1] = f32x16{};
+        for (int ut = 0; ut < 2; ++ut) acc[ut][0] = acc[ut][1] = f32x16{};
 #pragma unroll 4
         for (int ks = 0; ks < K / 16; ++ks) {
-            bf16x8 b[2];
+            bf16x8 w[2], x[2];
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-                b[ct] = *reinterpret_cast<const bf16x8*>(W + int64_t((wave * 2 + ct) * 32 + lr) * K + ks * 16 + lh * 8);
+            for (int ut = 0; ut < 2; ++ut)
+                w[ut] = *reinterpret_cast<const bf16x8*>(W + ((wave * 2 + ut) * 32 + lr) * K + ks * 16 + lh * 8);
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&in[rt * 32 + lr][ks * 16 + lh * 8]);
+            for (int rt = 0; rt < 2; ++rt) x[rt] = *reinterpret_cast<const bf16x8*>(&in[rt * 32 + lr][ks * 16 + lh * 8]);
 #pragma unroll
-                for (int ct = 0; ct < 2; ++ct)
-                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[ct], acc[rt][ct], 0, 0, 0);
+            for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+                    acc[ut][rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[ut], x[rt], acc[ut][rt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int n = (wave * 2 + ut) * 32 + g * 8 + lh * 4;   // units n .. n+3
+                const float4 bn = *reinterpret_cast<const float4*>(bias + n);
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) {
+                    const f32x16& c = acc[ut][rt];
+                    const uint32_t lo = uint32_t(f2bf(silu(c[4 * g] + bn.x))) |
+                                        uint32_t(f2bf(silu(c[4 * g + 1] + bn.y))) << 16;
+                    const uint32_t hi = uint32_t(f2bf(silu(c[4 * g + 2] + bn.z))) |
+                                        uint32_t(f2bf(silu(c[4 * g + 3] + bn.w))) << 16;
+                    *reinterpret_cast<uint2*>(&out[rt * 32 + lr][n]) = make_uint2(lo, hi);
+                }
             }
-        }
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            const int n = (wave * 2 + ct) * 32 + lr;
-            const float bn = bias[n];
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    out[rt * 32 + (r >> 2) * 8 + lh * 4 + (r & 3)][n] = f2bf(silu(acc[rt][ct][r] + bn));
-        }
         __syncthreads();
     }
-    // output unit: act[0] holds the last hidden layer; two threads per row
-    const int mrow = t >> 1, half = t & 1;
+    // output unit: act[0] holds the last hidden layer; four threads per row
+    const int mrow = t >> 2, q = t & 3;
     float h = 0.0f;
-    const float* w5 = par + OFF_W5 + half * (H / 2);
-    for (int j = 0; j < H / 2; ++j) h += bf2f(act[0][mrow][half * (H / 2) + j]) * w5[j];
+    const float4* w5 = reinterpret_cast<const float4*>(par + OFF_W5 + q * 64);
+    const uint4* ar = reinterpret_cast<const uint4*>(&act[0][mrow][q * 64]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint4 a8 = ar[j];
+        const float4 wa = w5[2 * j], wb = w5[2 * j + 1];
+        h += __uint_as_float(a8.x << 16) * wa.x + __uint_as_float(a8.x & 0xffff0000u) * wa.y;
+        h += __uint_as_float(a8.y << 16) * wa.z + __uint_as_float(a8.y & 0xffff0000u) * wa.w;
+        h += __uint_as_float(a8.z << 16) * wb.x + __uint_as_float(a8.z & 0xffff0000u) * wb.y;
+        h += __uint_as_float(a8.w << 16) * wb.z + __uint_as_float(a8.w & 0xffff0000u) * wb.w;
+    }
     h += __shfl_xor(h, 1);
-    const int64_t r = r0 + mrow;
-    if (half == 0 && r < rows) {
-        const int k = int(r % P);
+    h += __shfl_xor(h, 2);
+    const int r = r0 + mrow;
+    if (q == 0 && r < rows) {
+        const int k = r % P;
         const int64_t e = e0 + r / P;
         const float yh = float(kappa[k] - 1.0) * (h + par[OFF_B5]);
         const double w = w_in ? w_in[e] : 1.0;
@@ -893,7 +917,7 @@ mgrw_status mgrw_reweight_surrogate(mgrw_process* p, const double* mom, const do
         hipLaunchKernelGGL(features_kernel, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, mom, n_ext,
                            n_events, e0, 1, kap.p, ne, s->x0.p, s->kd.p);
         hipLaunchKernelGGL(mlp_infer_kernel, dim3(unsigned((rows + FR - 1) / FR)), dim3(256), 0, st, s->x0.p, P,
-                           kap.p, rows, e0, n_events, s->pbf.p, s->par.p, w_in, w_out);
+                           kap.p, int(rows), e0, n_events, s->pbf.p, s->par.p, w_in, w_out);
     }
     HIPCHK(hipGetLastError());
 
