@@ -45,15 +45,19 @@ constexpr int K_IN[4] = {K0, H, H, H};
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
-// float -> bfloat16 bits, round to nearest even (finite inputs)
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
+// float -> bfloat16 bits, round to nearest even (the hardware conversion)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
+// two floats -> two bfloat16 in one 32-bit word (a in the low half)
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    typedef __attribute__((ext_vector_type(2))) float f32x2;
+    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2));
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 
-__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// 1 / (1 + e^-z) with the hardware reciprocal (1 ulp): the activation is
+// rounded to bfloat16 afterwards
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float dsilu(float z) {
     float s = sigmoid(z);
@@ -471,10 +475,8 @@ mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restri
 #pragma unroll
                 for (int rt = 0; rt < 2; ++rt) {
                     const f32x16& c = acc[ut][rt];
-                    const uint32_t lo = uint32_t(f2bf(silu(c[4 * g] + bn.x))) |
-                                        uint32_t(f2bf(silu(c[4 * g + 1] + bn.y))) << 16;
-                    const uint32_t hi = uint32_t(f2bf(silu(c[4 * g + 2] + bn.z))) |
-                                        uint32_t(f2bf(silu(c[4 * g + 3] + bn.w))) << 16;
+                    const uint32_t lo = pack_bf16(silu(c[4 * g] + bn.x), silu(c[4 * g + 1] + bn.y));
+                    const uint32_t hi = pack_bf16(silu(c[4 * g + 2] + bn.z), silu(c[4 * g + 3] + bn.w));
                     *reinterpret_cast<uint2*>(&out[rt * 32 + lr][n]) = make_uint2(lo, hi);
                 }
             }
