@@ -405,41 +405,38 @@ __global__ void audit_kernel(const int64_t* __restrict__ idx, int64_t na, const 
 
 // ------------------------------------------------- fused inference
 //
-// All four hidden layers and the output unit for 64 feature rows per
-// workgroup: the rows' activations stay in LDS (two 64 x 256 bfloat16
-// buffers, 67.6 KB, so two workgroups share a CU and one's epilogue overlaps
-// the other's matrix work).  Each wave computes 64 units x 64 rows of a layer
-// on v_mfma_f32_32x32x16_bf16 as D = W A^T: the weights (rows of the
-// L2-resident bfloat16 copy) are the first operand, the activations the
-// second, so that a lane's four consecutive accumulator rows are four
-// consecutive units of one feature row and the epilogue (bias, SiLU, rounding
-// to bfloat16) stores them as one 8-byte word.  Rows are event-major
-// (r = e P + k): layer 1 reads the event's features (computed once per event)
-// and the point's kappa.  Same arithmetic as the layer-by-layer training
-// kernels.  rows < 2^31.
-constexpr int FR = 64;          // rows per workgroup
+// All four hidden layers and the output unit for 128 feature rows per
+// workgroup.  The rows' activations stay in one LDS buffer (128 x 256
+// bfloat16, 67.6 KB, so two workgroups share a CU and one's epilogue overlaps
+// the other's matrix work), updated in place: each wave computes 64 units x
+// 128 rows of a layer into registers on v_mfma_f32_32x32x16_bf16, the
+// workgroup synchronises, and the epilogue (bias, SiLU, rounding to bfloat16)
+// overwrites the layer's input.  The product is D = W A^T: the weights (rows
+// of the L2-resident bfloat16 copy, each read once per workgroup) are the
+// first operand, the activations the second, so a lane's four consecutive
+// accumulator rows are four consecutive units of one feature row, stored as
+// one 8-byte word.  Rows are event-major (r = e P + k): layer 1 reads the
+// event's features (computed once per event) and the point's kappa.  Same
+// arithmetic as the layer-by-layer training kernels.  rows < 2^31.
+constexpr int FR = 128;         // rows per workgroup
 constexpr int LDA = H + 8;      // LDS row stride (bfloat16)
 
 __global__ void __launch_bounds__(256, 2)
 mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restrict__ kappa, int rows, int64_t e0,
                  int64_t n_events, const uint16_t* __restrict__ wbf, const float* __restrict__ par,
                  const double* __restrict__ w_in, double* __restrict__ w_out) {
-    __shared__ __align__(16) uint16_t act[2][FR][LDA];
+    __shared__ __align__(16) uint16_t act[FR][LDA];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63, lr = lane & 31, lh = lane >> 5;
     const int r0 = int(blockIdx.x) * FR;
     {
-        // layer-1 input: 4 threads per row, 16 columns each
-        const int mrow = t >> 2, q = t & 3, r = r0 + mrow;
-        uint4 v0 = {0, 0, 0, 0}, v1 = {0, 0, 0, 0};
-        if (r < rows) {
-            const uint4* src = reinterpret_cast<const uint4*>(xev + int64_t(r / P) * K0 + q * 16);
-            v0 = src[0];
-            v1 = src[1];
-        }
-        uint4* dst = reinterpret_cast<uint4*>(&act[0][mrow][q * 16]);
-        dst[0] = v0;
-        dst[1] = v1;
-        if (q == 1 && r < rows) act[0][mrow][NRAW - 1] = f2bf(float((kappa[r % P] - 1.0) / 0.2));
+        // layer-1 input: 2 threads per row, 32 columns each
+        const int mrow = t >> 1, q = t & 1, r = r0 + mrow;
+        const bool live = r < rows;
+        const uint4* src = reinterpret_cast<const uint4*>(xev + int64_t((live ? r : 0) / P) * K0 + q * 32);
+        uint4* dst = reinterpret_cast<uint4*>(&act[mrow][q * 32]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dst[i] = live ? src[i] : make_uint4(0u, 0u, 0u, 0u);
+        if (q == 0 && r < rows) act[mrow][NRAW - 1] = f2bf(float((kappa[r % P] - 1.0) / 0.2));
     }
     __syncthreads();
 #pragma unroll 1
@@ -447,25 +444,26 @@ mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restri
         const int K = K_IN[l];
         const uint16_t* W = wbf + W_OFF[l];   // [H][K]
         const float* bias = par + B_OFF[l];
-        uint16_t (*in)[LDA] = act[l & 1];
-        uint16_t (*out)[LDA] = act[(l + 1) & 1];
-        f32x16 acc[2][2];   // [unit tile][row tile]
+        f32x16 acc[2][4];   // [unit tile][row tile]
 #pragma unroll
-        for (int ut = 0; ut < 2; ++ut) acc[ut][0] = acc[ut][1] = f32x16{};
-#pragma unroll 4
+        for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) acc[ut][rt] = f32x16{};
+#pragma unroll 2
         for (int ks = 0; ks < K / 16; ++ks) {
-            bf16x8 w[2], x[2];
+            bf16x8 w[2], x[4];
 #pragma unroll
             for (int ut = 0; ut < 2; ++ut)
                 w[ut] = *reinterpret_cast<const bf16x8*>(W + ((wave * 2 + ut) * 32 + lr) * K + ks * 16 + lh * 8);
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt) x[rt] = *reinterpret_cast<const bf16x8*>(&in[rt * 32 + lr][ks * 16 + lh * 8]);
+            for (int rt = 0; rt < 4; ++rt) x[rt] = *reinterpret_cast<const bf16x8*>(&act[rt * 32 + lr][ks * 16 + lh * 8]);
 #pragma unroll
-            for (int ut = 0; ut < 2; ++ut)
+            for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt)
+                for (int ut = 0; ut < 2; ++ut)
                     acc[ut][rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[ut], x[rt], acc[ut][rt], 0, 0, 0);
         }
+        __syncthreads();   // every wave has read the layer's input
 #pragma unroll
         for (int ut = 0; ut < 2; ++ut)
 #pragma unroll
@@ -473,22 +471,22 @@ mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restri
                 const int n = (wave * 2 + ut) * 32 + g * 8 + lh * 4;   // units n .. n+3
                 const float4 bn = *reinterpret_cast<const float4*>(bias + n);
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt) {
+                for (int rt = 0; rt < 4; ++rt) {
                     const f32x16& c = acc[ut][rt];
                     const uint32_t lo = pack_bf16(silu(c[4 * g] + bn.x), silu(c[4 * g + 1] + bn.y));
                     const uint32_t hi = pack_bf16(silu(c[4 * g + 2] + bn.z), silu(c[4 * g + 3] + bn.w));
-                    *reinterpret_cast<uint2*>(&out[rt * 32 + lr][n]) = make_uint2(lo, hi);
+                    *reinterpret_cast<uint2*>(&act[rt * 32 + lr][n]) = make_uint2(lo, hi);
                 }
             }
         __syncthreads();
     }
-    // output unit: act[0] holds the last hidden layer; four threads per row
-    const int mrow = t >> 2, q = t & 3;
+    // output unit on the last hidden layer; two threads per row
+    const int mrow = t >> 1, q = t & 1;
     float h = 0.0f;
-    const float4* w5 = reinterpret_cast<const float4*>(par + OFF_W5 + q * 64);
-    const uint4* ar = reinterpret_cast<const uint4*>(&act[0][mrow][q * 64]);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    const float4* w5 = reinterpret_cast<const float4*>(par + OFF_W5 + q * 128);
+    const uint4* ar = reinterpret_cast<const uint4*>(&act[mrow][q * 128]);
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
         const uint4 a8 = ar[j];
         const float4 wa = w5[2 * j], wb = w5[2 * j + 1];
         h += __uint_as_float(a8.x << 16) * wa.x + __uint_as_float(a8.x & 0xffff0000u) * wa.y;
@@ -497,7 +495,6 @@ mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restri
         h += __uint_as_float(a8.w << 16) * wb.z + __uint_as_float(a8.w & 0xffff0000u) * wb.w;
     }
     h += __shfl_xor(h, 1);
-    h += __shfl_xor(h, 2);
     const int r = r0 + mrow;
     if (q == 0 && r < rows) {
         const int k = r % P;
