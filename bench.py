@@ -142,6 +142,79 @@ def kpoly_leg(args, proc, mom, exact_out, stream, torch):
                          "frac": achieved / peak, "kernel_ms": kms, "flops_per_event": fpe}}
 
 
+def time_calls(fn, reps, stream, torch):
+    """Mean, min and max device time (ms) of `reps` calls of fn after one warm-up."""
+    fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for s, e in ev:
+        s.record(stream)
+        fn()
+        e.record(stream)
+    torch.cuda.synchronize()
+    t = [s.elapsed_time(e) for s, e in ev]
+    return float(np.mean(t)), float(np.min(t)), float(np.max(t))
+
+
+def end_to_end_leg(args, proc, mom_np, mom, out, stream, torch):
+    """The same call with the events in (pinned) host memory and the weights
+    copied back: host-to-device copy of the momenta, the reweight, the
+    device-to-host copy of the weights, each timed with device events."""
+    h_mom = torch.empty(mom_np.shape, dtype=torch.float64, pin_memory=True)
+    h_mom.numpy()[...] = mom_np
+    h_out = torch.empty(tuple(out.shape), dtype=torch.float64, pin_memory=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    best = None
+    for _ in range(2):   # the first pass warms the copy engines
+        ev[0].record(stream)
+        mom.copy_(h_mom, non_blocking=True)
+        ev[1].record(stream)
+        proc.reweight(mom, out=out)
+        ev[2].record(stream)
+        h_out.copy_(out, non_blocking=True)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        best = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    total = float(sum(best))
+    return {"value": args.n * args.points / (total * 1e-3), "unit": "events*points/s", "ms_per_step": total,
+            "h2d_ms": best[0], "reweight_ms": best[1], "d2h_ms": best[2],
+            "h2d_bytes": int(mom_np.nbytes), "d2h_bytes": int(out.numel() * 8),
+            "path": "events in pinned host memory: copy in, exact reweight, weights copied out"}
+
+
+def sweep(args, mom_np, kappa_points, mg, torch):
+    """Run time against the number of events (16 points) and against the
+    number of points (2^21 events): the paper's two scaling studies (Sec. 3.3)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n_sweep, p_sweep = [], []
+    proc = mg.Process(args.proc, args.prec)
+    proc.set_params([{"kappa_ttg": float(k)} for k in kappa_points(16)])
+    for e in list(range(10, 23, 2)) + [23]:
+        n = min(1 << e, mom_np.shape[2])
+        mom = torch.from_numpy(np.ascontiguousarray(mom_np[:, :, :n])).to(dev)
+        out = torch.empty((16, n), dtype=torch.float64, device=dev)
+        ms, lo, hi = time_calls(lambda: proc.reweight(mom, out=out), 3, stream, torch)
+        log(f"sweep N={n}: {ms:.2f} ms")
+        n_sweep.append({"events": n, "ms": ms, "min_ms": lo, "max_ms": hi,
+                        "events_points_per_s": n * 16 / (ms * 1e-3)})
+        del mom, out
+    n = min(1 << 21, mom_np.shape[2])
+    mom = torch.from_numpy(np.ascontiguousarray(mom_np[:, :, :n])).to(dev)
+    for P in (1, 2, 4, 8, 16, 32, 64):
+        pr = mg.Process(args.proc, args.prec)
+        pr.set_params([{"kappa_ttg": float(k)} for k in kappa_points(P)])
+        out = torch.empty((P, n), dtype=torch.float64, device=dev)
+        ms, lo, hi = time_calls(lambda: pr.reweight(mom, out=out), 3, stream, torch)
+        log(f"sweep P={P}: {ms:.2f} ms")
+        p_sweep.append({"points": P, "ms": ms, "min_ms": lo, "max_ms": hi,
+                        "events_points_per_s": n * P / (ms * 1e-3)})
+        del out, pr
+    return {"metric": f"reweight call time vs events and vs points, {args.proc}, {args.prec} precision",
+            "unit": "ms", "n_gpus": 1, "data": "synthetic", "events_sweep_points": 16,
+            "points_sweep_events": n, "events_sweep": n_sweep, "points_sweep": p_sweep}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +231,9 @@ def main():
     ap.add_argument("--train-events", type=int, default=1 << 21)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--audit", type=float, default=0.01)
+    ap.add_argument("--no-end-to-end", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line: call time against events and against points")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -174,6 +250,11 @@ def main():
     log(f"generating {args.n} {args.proc} events")
     mom_np = generate_events(args.proc, args.n)
     dev = torch.device("cuda:0")
+    if args.sweep:
+        if args.proc == "ee_5a":
+            sys.exit("--sweep covers the QCD processes")
+        print(json.dumps(sweep(args, mom_np, kappa_points, mg, torch)), flush=True)
+        return
     mom = torch.from_numpy(mom_np).to(dev)
     if args.proc == "ee_5a":
         kap = alpha_points(args.points)
@@ -247,6 +328,9 @@ def main():
                      "kernel": "amplitude kernel (one event per wave)", "kernel_ms": kms,
                      "flops_per_event": fpe, "per_helicity_flops": fcounts["per_helicity_flops"]},
     }
+    if not args.no_end_to_end:
+        log("end-to-end (host buffers)")
+        res["end_to_end"] = end_to_end_leg(args, proc, mom_np, mom, out, stream, torch)
     if not args.no_kpoly and args.proc in ("gg_tt", "gg_ttg", "gg_ttgg", "ee_5a"):
         log("kappa-polynomial variant")
         res["kpoly"] = kpoly_leg(args, proc, mom, out, stream, torch)
