@@ -296,6 +296,16 @@ mgrw_status mgrw_reweight_surrogate(mgrw_process *p, const double *mom, const do
 mgrw_status mgrw_surrogate_get(const mgrw_process *p, float *params);
 mgrw_status mgrw_surrogate_set(mgrw_process *p, const float *params);
 
+/* Checkpoint the surrogate to a file and back.  Format: the 8 bytes
+ * "MGRWSUR1", uint32 n_params (= MGRW_SURROGATE_N_PARAMS), uint32 0, then the
+ * n_params float32 parameters in the order above, all little-endian.  _save
+ * needs a trained or loaded surrogate (MGRW_ERR_STATE), writes path.part and
+ * renames it.  _load reads and checks the whole file (MGRW_ERR_ARG: missing,
+ * short, wrong magic or count) before it replaces the handle's network, as
+ * _set does; Adam moments start from zero.  Synchronous. */
+mgrw_status mgrw_surrogate_save(const mgrw_process *p, const char *path);
+mgrw_status mgrw_surrogate_load(mgrw_process *p, const char *path);
+
 /* One forward and backward pass over m given samples (device arrays):
  * x[m][MGRW_SURROGATE_N_FEATURES] features, kd[m] = kappa - 1, y[m] targets; pred[m] (device)
  * receives yhat, grad (host, MGRW_SURROGATE_N_PARAMS floats) the gradient of

@@ -94,6 +94,9 @@ def lib():
     L.mgrw_surrogate_get.restype = ctypes.c_int
     L.mgrw_surrogate_set.argtypes = [vp, fp]
     L.mgrw_surrogate_set.restype = ctypes.c_int
+    for name in ("mgrw_surrogate_save", "mgrw_surrogate_load"):
+        getattr(L, name).argtypes = [vp, ctypes.c_char_p]
+        getattr(L, name).restype = ctypes.c_int
     L.mgrw_surrogate_fwd_bwd.argtypes = [vp, vp, vp, vp, i64, vp, fp, ctypes.POINTER(ctypes.c_double), vp]
     L.mgrw_surrogate_fwd_bwd.restype = ctypes.c_int
     L.mgrw_reweight_kpoly.argtypes = [vp, dp, dp, i64, dp, dp, vp]
@@ -288,6 +291,14 @@ class Process:
         if p.size != SURROGATE_N_PARAMS:
             raise ValueError("wrong number of parameters")
         check(lib().mgrw_surrogate_set(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def save_surrogate(self, path):
+        """Write the network to a checkpoint file (mgrw_surrogate_save)."""
+        check(lib().mgrw_surrogate_save(self._h, os.fsencode(path)))
+
+    def load_surrogate(self, path):
+        """Replace the network by a checkpoint file's (mgrw_surrogate_load)."""
+        check(lib().mgrw_surrogate_load(self._h, os.fsencode(path)))
 
     def surrogate_fwd_bwd(self, x, kd, y, stream=None):
         """One forward/backward pass on device float32 x [m, 53], kd [m], y [m]."""

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -36,6 +37,7 @@ constexpr int64_t OFF_B4 = OFF_W4 + int64_t(H) * H;
 constexpr int64_t OFF_W5 = OFF_B4 + H;
 constexpr int64_t OFF_B5 = OFF_W5 + H;
 constexpr int64_t NPAR = OFF_B5 + 1;
+constexpr char kCheckpointMagic[9] = "MGRWSUR1";
 static_assert(NPAR == MGRW_SURROGATE_N_PARAMS, "parameter layout");
 
 constexpr int64_t W_OFF[4] = {OFF_W1, OFF_W2, OFF_W3, OFF_W4};
@@ -783,6 +785,44 @@ mgrw_status mgrw_surrogate_get(const mgrw_process* p, float* params) {
     if (!p->sur || !p->sur->par.p) return set_error(MGRW_ERR_STATE, "no surrogate");
     HIPCHK(hipMemcpy(params, p->sur->par.p, NPAR * sizeof(float), hipMemcpyDeviceToHost));
     return MGRW_OK;
+}
+
+mgrw_status mgrw_surrogate_save(const mgrw_process* p, const char* path) {
+    if (!p || !path) return set_error(MGRW_ERR_ARG, "null argument");
+    if (!p->sur || !p->sur->par.p) return set_error(MGRW_ERR_STATE, "no surrogate");
+    std::vector<float> w(static_cast<size_t>(NPAR));
+    mgrw_status st = mgrw_surrogate_get(p, w.data());
+    if (st != MGRW_OK) return st;
+    const std::string tmp = std::string(path) + ".part";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return set_error(MGRW_ERR_ARG, std::string("cannot write ") + tmp);
+    const uint32_t head[2] = {uint32_t(NPAR), 0u};
+    bool ok = std::fwrite(kCheckpointMagic, 1, 8, f) == 8 && std::fwrite(head, sizeof head, 1, f) == 1 &&
+              std::fwrite(w.data(), sizeof(float), w.size(), f) == w.size();
+    if (std::fclose(f) != 0) ok = false;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return set_error(MGRW_ERR_ARG, std::string("writing ") + path + " failed");
+    }
+    return MGRW_OK;
+}
+
+mgrw_status mgrw_surrogate_load(mgrw_process* p, const char* path) {
+    if (!p || !path) return set_error(MGRW_ERR_ARG, "null argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return set_error(MGRW_ERR_ARG, std::string("cannot open ") + path);
+    char magic[8];
+    uint32_t head[2];
+    std::vector<float> w(static_cast<size_t>(NPAR));
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kCheckpointMagic, 8) == 0 &&
+              std::fread(head, sizeof head, 1, f) == 1 && head[0] == uint32_t(NPAR) &&
+              std::fread(w.data(), sizeof(float), w.size(), f) == w.size();
+    const bool at_end = ok && std::fgetc(f) == EOF;
+    std::fclose(f);
+    if (!ok || !at_end)
+        return set_error(MGRW_ERR_ARG, std::string(path) + ": not a surrogate checkpoint of " +
+                                           std::to_string(NPAR) + " parameters");
+    return mgrw_surrogate_set(p, w.data());
 }
 
 mgrw_status mgrw_surrogate_fwd_bwd(mgrw_process* p, const float* x, const float* kd, const float* y, int64_t m,

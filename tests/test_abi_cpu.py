@@ -3,6 +3,7 @@ argument validation that needs no device (no kernel is launched)."""
 import ctypes
 import os
 import re
+import struct
 
 import pytest
 
@@ -99,3 +100,27 @@ def test_unsupported_precisions_and_processes(L):
     assert L.mgrw_create_process(bd.EE_5A + 1, bd.FP64, ctypes.byref(base), ctypes.byref(h)) == bd.ERR_ARG
     assert L.mgrw_create_process(bd.EE_5A, bd.FP64, ctypes.byref(base), ctypes.byref(h)) == bd.OK
     L.mgrw_destroy_process(h)
+
+
+def test_surrogate_checkpoint_errors(L, tmp_path):
+    """Checkpoint files are checked in full before the device is touched."""
+    p = bd.Process("gg_ttg", "mixed")
+    assert L.mgrw_surrogate_save(p._h, str(tmp_path / "x.sur").encode()) == bd.ERR_STATE   # no network
+    assert L.mgrw_surrogate_load(p._h, str(tmp_path / "missing.sur").encode()) == bd.ERR_ARG
+    n = bd.SURROGATE_N_PARAMS
+    good_head = b"MGRWSUR1" + struct.pack("<II", n, 0)
+    cases = {
+        "magic.sur": b"MGRWSUR2" + struct.pack("<II", n, 0) + bytes(4 * n),
+        "count.sur": b"MGRWSUR1" + struct.pack("<II", n - 1, 0) + bytes(4 * (n - 1)),
+        "short.sur": good_head + bytes(4 * n - 4),
+        "long.sur": good_head + bytes(4 * n + 4),
+        "empty.sur": b"",
+    }
+    for name, data in cases.items():
+        f = tmp_path / name
+        f.write_bytes(data)
+        assert L.mgrw_surrogate_load(p._h, str(f).encode()) == bd.ERR_ARG, name
+        assert b"checkpoint" in L.mgrw_last_error(), name
+    assert L.mgrw_surrogate_load(None, str(tmp_path / "magic.sur").encode()) == bd.ERR_ARG
+    assert L.mgrw_surrogate_load(p._h, None) == bd.ERR_ARG
+    p.close()

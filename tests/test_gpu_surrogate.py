@@ -140,6 +140,34 @@ def test_audit_selection_is_the_counter_hash(torch_dev, trained_ttg):
     assert int(st[0, 4]) == int(expect.sum())
 
 
+def test_checkpoint_round_trip(torch_dev, tmp_path):
+    """save -> load into another handle gives the same parameters bit for bit
+    and the same surrogate weights; the file has the documented layout."""
+    import struct
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    say("case surrogate checkpoint round trip")
+    params = mlp.init_params(21).astype(np.float32)
+    a = mg.Process("gg_ttg", "mixed")
+    a.set_surrogate_params(params)
+    path = tmp_path / "net.sur"
+    a.save_surrogate(path)
+    raw = path.read_bytes()
+    assert raw[:8] == b"MGRWSUR1" and struct.unpack("<II", raw[8:16]) == (mlp.N_PARAMS, 0)
+    assert np.array_equal(np.frombuffer(raw[16:], dtype="<f4"), params)
+    b = mg.Process("gg_ttg", "mixed")
+    b.load_surrogate(path)
+    assert np.array_equal(b.surrogate_params(), params)
+    kap = kappa_points(4)
+    mom = dev(torch, generate_events("gg_ttg", 700, first_event=3 * 10 ** 5))
+    outs = []
+    for p in (a, b):
+        p.set_params([{"kappa_ttg": float(k)} for k in kap])
+        o, _, _ = p.reweight_surrogate(mom, audit_fraction=1e-12, seed=1, max_audit_error=1.0)
+        outs.append(o.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.fixture(scope="module")
 def trained_ttg(torch_dev):
     import paper_2312_07440_amd as mg
