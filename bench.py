@@ -238,8 +238,9 @@ def main():
                     help="run one plain 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the reweighting is embarrassingly parallel over events and "
-              "this build measures one GPU's share; multi-GPU runs are not part of it.", file=sys.stderr)
+        print("bench.py runs on one GPU only: the reweighting is embarrassingly parallel over events, so "
+              "several GPUs take separate event batches, one process each; it measures one GPU's share.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
