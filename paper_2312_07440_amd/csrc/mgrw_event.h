@@ -67,14 +67,10 @@ constexpr int kpoly_pairs() {
     return Proc::NG * (Proc::NG + 1) / 2;
 }
 
-// Add one helicity configuration's B_ab (pair (a <= b) at b(b+1)/2 + a).
-// w: storage for the external wavefunctions (registers or an LDS slot).
-template <class Proc, typename T, typename KN, typename BS, typename EXT>
-MGRW_HD void kpoly_helicity(const KN& k, const BS& b, int h, double* B, EXT& w) {
-    typename Proc::template coup<T> c = {T(1), T(1), T(1)};
-    Proc::template external<T>(b, h, w);
-    cx<T> J[Proc::NG * Proc::K];
-    Proc::amplitude_kpoly(w, k, c, J);
+// Add the colour products of one helicity configuration's kappa-power
+// amplitudes J[NG K] to B (pair (a <= b) at b(b+1)/2 + a).
+template <class Proc, typename T>
+MGRW_HD void kpoly_colour(const cx<T>* J, double* B) {
 #if defined(__HIP_DEVICE_COMPILE__)
 #pragma unroll
 #endif
@@ -91,6 +87,17 @@ MGRW_HD void kpoly_helicity(const KN& k, const BS& b, int h, double* B, EXT& w) 
         for (int pa = 0; pa <= pb; ++pa)
             B[pb * (pb + 1) / 2 + pa] += double(Proc::template re_dot<TA, T>(J + pa * Proc::K, Z));
     }
+}
+
+// Add one helicity configuration's B_ab.
+// w: storage for the external wavefunctions (registers or an LDS slot).
+template <class Proc, typename T, typename KN, typename BS, typename EXT>
+MGRW_HD void kpoly_helicity(const KN& k, const BS& b, int h, double* B, EXT& w) {
+    typename Proc::template coup<T> c = {T(1), T(1), T(1)};
+    Proc::template external<T>(b, h, w);
+    cx<T> J[Proc::NG * Proc::K];
+    Proc::amplitude_kpoly(w, k, c, J);
+    kpoly_colour<Proc, T>(J, B);
 }
 
 template <class Proc, typename T, typename KN, typename BS>

@@ -291,6 +291,24 @@ qcd_kpoly_lane_kernel(const double* __restrict__ mom, const double* __restrict__
     kpoly_outputs<Proc>(B, a, n, e, (a.mode == 0 && w_in) ? w_in[e] : 1.0, out, me0_out);
 }
 
+// Accumulators of the kappa-polynomial program with the first NL complex
+// entries in the lane's LDS column (entry i at lds[i * S]) and the others in
+// registers; the program's indices are constants after inlining, so each
+// access resolves to one storage at compile time.
+template <typename T, int N, int NL, int S>
+struct split_acc {
+    cx<T>* lds;
+    cx<T> reg[N - NL];
+    __device__ __forceinline__ cx<T>& operator[](int i) { return i < NL ? lds[i * S] : reg[i - NL]; }
+};
+
+// Large single-precision programs (NG K >= 96 accumulators) keep half of
+// their kappa-power accumulators in LDS while the program runs.
+template <class Proc, typename T>
+constexpr bool kpoly_lds_split() {
+    return sizeof(T) == 4 && Proc::NG * Proc::K >= 96;
+}
+
 // One event per wave, helicity configurations on the lanes.
 template <class Proc, typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -303,7 +321,19 @@ qcd_kpoly_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* 
 #pragma unroll 1
     for (int hc = 0; hc < Proc::NHEL; hc += 64) {
         __asm__ volatile("" ::: "memory");
-        if constexpr (sizeof(T) == 8) {
+        if constexpr (kpoly_lds_split<Proc, T>()) {
+            constexpr int N = Proc::NG * Proc::K, NL = N / 2;
+            __shared__ cx<T> jl[NL * kBlock];
+            split_acc<T, N, NL, kBlock> acc{&jl[threadIdx.x]};
+            typename Proc::template ext<T> w;
+            typename Proc::template coup<T> c = {T(1), T(1), T(1)};
+            Proc::template external<T>(ev[e].b, hc + lane, w);
+            Proc::amplitude_kpoly(w, ev[e].k, c, acc);
+            cx<T> J[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) J[i] = acc[i];
+            kpoly_colour<Proc, T>(J, B);
+        } else if constexpr (sizeof(T) == 8) {
             // double precision: external wavefunctions in the lane's own LDS
             // slot, as in qcd_wave_kernel (10 % faster for g g -> t tbar g g;
             // in single precision registers are faster)

@@ -709,8 +709,13 @@ def emit_process(name, ng, chunks=1):
         kbody = ek.program()
         w("  // Same diagrams at unit couplings, J[(k-1)*K + w] collecting the diagrams")
         w("  // with k top-gluon vertices: J(g, kappa) = g^NG sum_k kappa^k J_k.")
-        w("  template <typename T, typename KN>")
-        w("  static MGRW_HD void amplitude_kpoly(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {")
+        w("  // J: a pointer, or an accessor object with operator[] (entries kept partly")
+        w("  // outside registers).")
+        w("  template <typename T, typename KN, typename JA>")
+        w("  static MGRW_HD void amplitude_kpoly(const ext<T>& w, const KN& k, const coup<T>& c, JA&& J) {")
+        w("#if defined(__HIP_DEVICE_COMPILE__)")
+        w("#pragma unroll")
+        w("#endif")
         w("    for (int i = 0; i < NG * K; ++i) J[i] = {T(0), T(0)};")
         for line in kbody:
             w("    " + line)
