@@ -61,20 +61,31 @@ def flops_per_event(proc, n_points_total, n_hel):
 def cpu_baseline(proc, ng, mom_np, kap, gpu_out, sample, points_per_event):
     """The oracle (FP64, OpenMP) on a bounded sample of the same workload."""
     import oracle
-    sub = np.ascontiguousarray(mom_np[:, :, :sample])
-    t0 = time.perf_counter()
-    if proc == "ee_5a":
-        me = oracle.ee_photons_me(sub, [ALPHA0] + [float(a) for a in kap])
-    else:
-        me = oracle.qcd_me(ng, sub, [(0.118, 173.0, 1.0)] + [(0.118, 173.0, float(k)) for k in kap])
-    w = oracle.reweight(me)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def run(m):
+        sub = np.ascontiguousarray(mom_np[:, :, :m])
+        t0 = time.perf_counter()
+        if proc == "ee_5a":
+            me = oracle.ee_photons_me(sub, [ALPHA0] + [float(a) for a in kap])
+        else:
+            me = oracle.qcd_me(ng, sub, [(0.118, 173.0, 1.0)] + [(0.118, 173.0, float(k)) for k in kap])
+        w = oracle.reweight(me)
+        return w, time.perf_counter() - t0
+
+    cores = oracle.max_threads()
+    w, dt = run(sample)
     err = np.abs(gpu_out[:, :sample] / w - 1)
+    # one thread on a sixteenth of the sample
+    oracle.set_threads(1)
+    s1 = max(1, sample // 16)
+    _, dt1 = run(s1)
+    oracle.set_threads(cores)
     return {"value": sample * points_per_event / dt, "unit": "events*points/s", "cores": cores,
             "kind": "oracle",
             "sample": f"first {sample} events of the same sample, base + {len(kap)} points, FP64 oracle "
-                      f"({dt:.1f} s wall)"}, float(err.max()), float(np.median(err))
+                      f"({dt:.1f} s wall)",
+            "single_thread": {"value": s1 * points_per_event / dt1, "events": s1, "seconds": dt1}}, \
+        float(err.max()), float(np.median(err))
 
 
 def surrogate_leg(args, proc, mom, exact_out, kap, torch, generate_events):

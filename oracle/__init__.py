@@ -116,6 +116,16 @@ def ew_points(points):
     return arr
 
 
+def set_threads(n):
+    """Number of OpenMP threads the oracle's event loops use (timing only)."""
+    _lib(False)[0].orc_set_threads(int(n))
+
+
+def max_threads():
+    """Threads the oracle's event loops use now."""
+    return int(_lib(False)[0].orc_max_threads())
+
+
 def qcd_me(ng, mom, points, quad=False):
     """|M|^2 [npts, n] for SoA momenta `mom` (ng+2, 4, n)."""
     mom = np.ascontiguousarray(mom, dtype=np.float64)

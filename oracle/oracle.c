@@ -41,6 +41,7 @@
  * no precomputation beyond the external wavefunctions.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -549,6 +550,10 @@ int API(qcd_flows)(int ng, const double *mom_aos, const int *hel, const orc_qcd_
 
 /* |M|^2 of g g -> t tbar + (ng-2) g for every event and parameter point.
  * mom: SoA [ng+2][4][n]; me: [npts][n]; cf: [K][K] colour matrix. */
+/* Threads of the OpenMP loops (timing of the oracle only). */
+void API(set_threads)(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int API(max_threads)(void) { return omp_get_max_threads(); }
+
 int API(qcd_me)(int ng, const double *mom, int64_t n, const orc_qcd_point *pts, int npts,
                 const double *cf, double *me) {
     if (ng < 2 || ng > MAXG || n < 0 || npts < 1) return -1;
