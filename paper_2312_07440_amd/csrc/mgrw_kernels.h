@@ -95,14 +95,20 @@ __device__ __forceinline__ void run_points(const KN& k, const BS& b, const qcd_l
 }
 
 // Lanes per workgroup of the one-event-per-lane kernel: in single precision
-// each lane owns an LDS slot for its kinematics and bases, so large processes
-// use smaller workgroups to stay within the 160 KiB of LDS.
+// each lane owns an LDS slot for its kinematics and bases, and the workgroup
+// size is the one of 256, 128, 64 that keeps the most waves resident per CU
+// within its 160 KiB of LDS (larger on ties).
+constexpr int lane_waves_per_cu(size_t slot, int nb) {
+    return slot * nb <= 160 * 1024 ? int((160 * 1024) / (slot * nb)) * (nb / 64) : 0;
+}
 template <class Proc, typename T>
 constexpr int lane_block() {
     if constexpr (sizeof(T) == 4) {
         constexpr size_t slot = sizeof(lds_slot<typename Proc::template kin<T>>) +
                                 sizeof(lds_slot<typename Proc::template basis<T>>);
-        return slot * 256 <= 160 * 1024 ? 256 : (slot * 128 <= 160 * 1024 ? 128 : 64);
+        constexpr int w256 = lane_waves_per_cu(slot, 256), w128 = lane_waves_per_cu(slot, 128),
+                      w64 = lane_waves_per_cu(slot, 64);
+        return (w256 >= w128 && w256 >= w64) ? 256 : (w128 >= w64 ? 128 : 64);
     } else {
         return kBlock;
     }
