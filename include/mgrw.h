@@ -275,6 +275,18 @@ typedef struct {
 mgrw_status mgrw_surrogate_train(mgrw_process *p, const double *mom, int64_t n_events,
                                  const mgrw_train_config *cfg, double *loss_out, void *stream);
 
+/* Train the surrogate on m given samples instead of exact labels (device
+ * arrays, the layout of mgrw_surrogate_fwd_bwd): features x[m][53] (float32,
+ * rounded to bfloat16 like the computed ones), kd[m] (the factor the output
+ * unit is multiplied by), targets y[m].  Same network, initialisation, batches
+ * and Adam as mgrw_surrogate_train; the handle's process and points are not
+ * used (any handle may hold the network).  For fitting targets computed
+ * elsewhere and for checking the training on a known function.  Synchronous.
+ * Errors: MGRW_ERR_ARG (null pointers, m outside [batch, 2^31), bad
+ * configuration), MGRW_ERR_DEVICE, MGRW_ERR_ALLOC. */
+mgrw_status mgrw_surrogate_train_samples(mgrw_process *p, const float *x, const float *kd, const float *y, int64_t m,
+                                         const mgrw_train_config *cfg, double *loss_out, void *stream);
+
 /* Reweight with the surrogate and an exact audit.  Every event gets
  * w_out[k*n_events + e] = W_e exp(yhat); events selected by the audit (a
  * counter-based hash of (seed, e) below audit_fraction, in (0, 1]) are

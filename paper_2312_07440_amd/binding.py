@@ -86,6 +86,9 @@ def lib():
     L.mgrw_last_error.restype = ctypes.c_char_p
     L.mgrw_surrogate_train.argtypes = [vp, dp, i64, ctypes.POINTER(TrainConfig), ctypes.POINTER(ctypes.c_double), vp]
     L.mgrw_surrogate_train.restype = ctypes.c_int
+    L.mgrw_surrogate_train_samples.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(TrainConfig),
+                                               ctypes.POINTER(ctypes.c_double), vp]
+    L.mgrw_surrogate_train_samples.restype = ctypes.c_int
     L.mgrw_reweight_surrogate.argtypes = [vp, dp, dp, i64, ctypes.c_double, ctypes.c_uint64, ctypes.c_double, dp,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), vp]
     L.mgrw_reweight_surrogate.restype = ctypes.c_int
@@ -260,6 +263,19 @@ class Process:
         losses = np.zeros(int(epochs))
         check(lib().mgrw_surrogate_train(self._h, _ptr(mom, "mom"), n, ctypes.byref(cfg),
                                          losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(None)))
+        return losses
+
+    def train_surrogate_samples(self, x, kd, y, epochs=10, batch=16384, lr=1e-3, lr_decay=0.8, seed=3003):
+        """Fit the MLP to given device float32 samples x [m, 53], kd [m], y [m];
+        returns per-epoch losses."""
+        import numpy as np
+        m = x.shape[0]
+        cfg = TrainConfig(int(epochs), int(batch), float(lr), float(lr_decay), int(seed))
+        losses = np.zeros(int(epochs))
+        check(lib().mgrw_surrogate_train_samples(self._h, _fptr(x, "x", m * SURROGATE_N_FEATURES), _fptr(kd, "kd", m),
+                                                 _fptr(y, "y", m), m, ctypes.byref(cfg),
+                                                 losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 _stream(None)))
         return losses
 
     def reweight_surrogate(self, mom, w_in=None, audit_fraction=0.01, seed=2002, max_audit_error=0.01,

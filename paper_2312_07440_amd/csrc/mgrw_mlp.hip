@@ -758,6 +758,53 @@ mgrw_status upload_kappas(const mgrw_process* p, dbuf<double>& kap, hipStream_t 
     return MGRW_OK;
 }
 
+// Fit a freshly initialised network (seeded) to ns samples: bfloat16
+// feature rows xall [ns][64], kd = kappa - 1, targets y; Adam on shuffled
+// batches, per-epoch mean loss into loss_out (host, may be NULL).
+mgrw_status train_core(mgrw_process* p, const uint16_t* xall, const float* kdall, const float* yall, int64_t ns,
+                       const mgrw_train_config* cfg, double* loss_out, hipStream_t st) {
+    std::vector<float> w0;
+    init_params(w0, cfg->seed);
+    mgrw_status r = mgrw_surrogate_set(p, w0.data());
+    if (r != MGRW_OK) return r;
+    surrogate* s = p->sur;
+    const int64_t B = cfg->batch;
+    HIPCHK(ensure_rows(s, B));
+    const int64_t nb = ns / B;
+    if (nb < 1) return set_error(MGRW_ERR_ARG, "fewer samples than one batch");
+    std::vector<int32_t> perm(ns);
+    dbuf<int32_t> dperm;
+    HIPCHK(dperm.alloc(size_t(ns)));
+    float lr = float(cfg->lr);
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        for (int64_t i = 0; i < ns; ++i) perm[i] = int32_t(i);
+        for (int64_t i = ns - 1; i > 0; --i) {   // Fisher-Yates with a counter-based generator
+            int64_t j = int64_t(u01(cfg->seed + 7919 * uint64_t(ep + 1), 3, uint64_t(i)) * double(i + 1));
+            if (j > i) j = i;
+            std::swap(perm[i], perm[j]);
+        }
+        HIPCHK(hipMemcpyAsync(dperm.p, perm.data(), size_t(ns) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(s->lossd.p, 0, sizeof(double), st));
+        for (int64_t b = 0; b < nb; ++b) {
+            hipLaunchKernelGGL(gather_kernel, dim3(unsigned(B)), dim3(64), 0, st, dperm.p, b * B, int(B), xall,
+                               kdall, yall, s->x0.p, s->kd.p, s->y.p);
+            forward(s, B, true, st);
+            r = head_train(s, B, 1.0 / double(B), st);
+            if (r != MGRW_OK) return r;
+            r = backward(s, B, st);
+            if (r != MGRW_OK) return r;
+            adam(s, lr, st);
+        }
+        double lsum = 0.0;
+        HIPCHK(hipMemcpyAsync(&lsum, s->lossd.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (loss_out) loss_out[ep] = lsum / double(nb);
+        lr *= float(cfg->lr_decay);
+    }
+    HIPCHK(hipGetLastError());
+    return MGRW_OK;
+}
+
 }  // namespace
 }  // namespace mgrw
 
@@ -882,47 +929,27 @@ mgrw_status mgrw_surrogate_train(mgrw_process* p, const double* mom, int64_t n_e
                        int64_t(0), P, kap.p, ns, xall.p, kdall.p);
     HIPCHK(hipGetLastError());
 
-    // network
-    std::vector<float> w0;
-    init_params(w0, cfg->seed);
-    r = mgrw_surrogate_set(p, w0.data());
-    if (r != MGRW_OK) return r;
-    surrogate* s = p->sur;
-    const int64_t B = cfg->batch;
-    HIPCHK(ensure_rows(s, B));
-    const int64_t nb = ns / B;
-    if (nb < 1) return set_error(MGRW_ERR_ARG, "fewer samples than one batch");
-    std::vector<int32_t> perm(ns);
-    dbuf<int32_t> dperm;
-    HIPCHK(dperm.alloc(size_t(ns)));
-    float lr = float(cfg->lr);
-    for (int ep = 0; ep < cfg->epochs; ++ep) {
-        for (int64_t i = 0; i < ns; ++i) perm[i] = int32_t(i);
-        for (int64_t i = ns - 1; i > 0; --i) {   // Fisher-Yates with a counter-based generator
-            int64_t j = int64_t(u01(cfg->seed + 7919 * uint64_t(ep + 1), 3, uint64_t(i)) * double(i + 1));
-            if (j > i) j = i;
-            std::swap(perm[i], perm[j]);
-        }
-        HIPCHK(hipMemcpyAsync(dperm.p, perm.data(), size_t(ns) * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemsetAsync(s->lossd.p, 0, sizeof(double), st));
-        for (int64_t b = 0; b < nb; ++b) {
-            hipLaunchKernelGGL(gather_kernel, dim3(unsigned(B)), dim3(64), 0, st, dperm.p, b * B, int(B), xall.p,
-                               kdall.p, yall.p, s->x0.p, s->kd.p, s->y.p);
-            forward(s, B, true, st);
-            r = head_train(s, B, 1.0 / double(B), st);
-            if (r != MGRW_OK) return r;
-            r = backward(s, B, st);
-            if (r != MGRW_OK) return r;
-            adam(s, lr, st);
-        }
-        double lsum = 0.0;
-        HIPCHK(hipMemcpyAsync(&lsum, s->lossd.p, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (loss_out) loss_out[ep] = lsum / double(nb);
-        lr *= float(cfg->lr_decay);
-    }
+    return train_core(p, xall.p, kdall.p, yall.p, ns, cfg, loss_out, st);
+}
+
+mgrw_status mgrw_surrogate_train_samples(mgrw_process* p, const float* x, const float* kd, const float* y,
+                                         int64_t m, const mgrw_train_config* cfg, double* loss_out, void* stream) {
+    if (!p || !cfg || !x || !kd || !y) return set_error(MGRW_ERR_ARG, "null argument");
+    if (m <= 0 || m >= (int64_t(1) << 31)) return set_error(MGRW_ERR_ARG, "m must be in [1, 2^31)");
+    if (cfg->epochs < 1 || cfg->batch < 64 || cfg->batch % 64 != 0 || !(cfg->lr > 0))
+        return set_error(MGRW_ERR_ARG, "bad training configuration");
+    if (m < cfg->batch) return set_error(MGRW_ERR_ARG, "fewer samples than one batch");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    dbuf<uint16_t> xall;
+    dbuf<float> kdall, yall;
+    HIPCHK(xall.alloc(size_t(m) * K0));
+    HIPCHK(kdall.alloc(size_t(m)));
+    HIPCHK(yall.alloc(size_t(m)));
+    hipLaunchKernelGGL(features_from_f32, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, x, m, xall.p);
+    HIPCHK(hipMemcpyAsync(kdall.p, kd, size_t(m) * sizeof(float), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(yall.p, y, size_t(m) * sizeof(float), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipGetLastError());
-    return MGRW_OK;
+    return train_core(p, xall.p, kdall.p, yall.p, m, cfg, loss_out, st);
 }
 
 mgrw_status mgrw_reweight_surrogate(mgrw_process* p, const double* mom, const double* w_in, int64_t n_events,
