@@ -229,7 +229,7 @@ def sweep(args, mom_np, kappa_points, mg, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--proc", default="gg_ttgg")
     ap.add_argument("--n", type=int, default=1 << 23)
@@ -326,6 +326,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_min": float(np.min(step_ms)), "ms_max": float(np.max(step_ms)), "ms_median": float(np.median(step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
