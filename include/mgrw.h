@@ -124,6 +124,21 @@ mgrw_status mgrw_eval_me(mgrw_process *p, const double *mom, int64_t n_events, i
 mgrw_status mgrw_reweight(mgrw_process *p, const double *mom, const double *w_in, int64_t n_events,
                           double *w_out, double *me_base_out, void *stream);
 
+/* mgrw_reweight for events and weights in HOST memory (procedure steps 2-8
+ * with the transfers, which dominate small samples: Sec. 3.3).  mom
+ * ([n_ext][4][n_events]), w_in ([n_events], may be NULL), w_out
+ * ([n_points][n_events]) and me_base_out ([n_events], may be NULL) are host
+ * arrays in the layouts of mgrw_reweight, owned by the caller.  The batch is
+ * processed in chunks of `chunk` events (0: 2^18) on two streams of the
+ * library's own, so one chunk's copies overlap the other's kernels; pinned
+ * host memory makes the copies asynchronous (pageable memory works, without
+ * the overlap).  Synchronous: returns when w_out is written.  The results
+ * equal mgrw_reweight's bit for bit.  Errors: MGRW_ERR_ARG (null pointers,
+ * n_events < 0, chunk < 0), MGRW_ERR_STATE (no points), MGRW_ERR_ALLOC,
+ * MGRW_ERR_DEVICE. */
+mgrw_status mgrw_reweight_host(mgrw_process *p, const double *mom, const double *w_in, int64_t n_events,
+                               double *w_out, double *me_base_out, int64_t chunk);
+
 /* Exact reweighting by the kappa polynomial.  Same contract and results (to
  * rounding) as mgrw_reweight, by a different evaluation: every diagram carries
  * g_s^n kappa^k with k its number of top-gluon vertices, so one evaluation per

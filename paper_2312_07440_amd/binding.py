@@ -86,6 +86,8 @@ def lib():
     L.mgrw_last_error.restype = ctypes.c_char_p
     L.mgrw_surrogate_train.argtypes = [vp, dp, i64, ctypes.POINTER(TrainConfig), ctypes.POINTER(ctypes.c_double), vp]
     L.mgrw_surrogate_train.restype = ctypes.c_int
+    L.mgrw_reweight_host.argtypes = [vp, vp, vp, i64, vp, vp, i64]
+    L.mgrw_reweight_host.restype = ctypes.c_int
     L.mgrw_surrogate_train_samples.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(TrainConfig),
                                                ctypes.POINTER(ctypes.c_double), vp]
     L.mgrw_surrogate_train_samples.restype = ctypes.c_int
@@ -241,6 +243,37 @@ class Process:
                                   _ptr(out, "out", self.n_points * n),
                                   _ptr(me_base_out, "me_base_out", n, allow_none=True), _stream(stream)))
         return out
+
+    def reweight_host(self, mom, w_in=None, chunk=0, me_base=False, out=None):
+        """mgrw_reweight_host: events in host memory (numpy array or CPU
+        tensor, pinned for overlap), weights returned in a host array
+        [n_points, n] (`out`, else a new numpy array; and |M_base|^2 [n] if
+        me_base)."""
+        import numpy as np
+
+        def host_ptr(a, name, count):
+            if a is None:
+                return None
+            if hasattr(a, "data_ptr"):
+                if a.is_cuda or not a.is_contiguous() or a.dtype != __import__("torch").float64:
+                    raise ValueError(f"{name}: contiguous float64 CPU tensor expected")
+                if a.numel() < count:
+                    raise ValueError(f"{name}: {a.numel()} values, {count} needed")
+                return ctypes.c_void_p(a.data_ptr())
+            if a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"]:
+                raise ValueError(f"{name}: contiguous float64 array expected")
+            if a.size < count:
+                raise ValueError(f"{name}: {a.size} values, {count} needed")
+            return ctypes.c_void_p(a.ctypes.data)
+
+        n = int(mom.shape[-1])
+        if out is None:
+            out = np.empty((self.n_points, n))
+        me0 = np.empty(n) if me_base else None
+        check(lib().mgrw_reweight_host(self._h, host_ptr(mom, "mom", self.n_ext * 4 * n),
+                                       host_ptr(w_in, "w_in", n), n, host_ptr(out, "out", self.n_points * n),
+                                       host_ptr(me0, "me_base", n), int(chunk)))
+        return (out, me0) if me_base else out
 
     def reweight_kpoly(self, mom, w_in=None, out=None, me_base_out=None, stream=None):
         """Exact reweighting through the kappa polynomial (mgrw_reweight_kpoly)."""

@@ -43,7 +43,8 @@ def build(verbose=False, jobs=None):
     generate()
     os.makedirs(OBJ, exist_ok=True)
     units = [os.path.join(CSRC, "mgrw_abi.hip"), os.path.join(CSRC, "mgrw_mlp.hip"),
-             os.path.join(CSRC, "mgrw_qed.hip"), os.path.join(CSRC, "mgrw_multi.hip")] + \
+             os.path.join(CSRC, "mgrw_qed.hip"), os.path.join(CSRC, "mgrw_multi.hip"),
+             os.path.join(CSRC, "mgrw_stream.hip")] + \
         [os.path.join(GEN, u) for u in translation_units()]
     # the split program parts take longest: start them first
     units.sort(key=lambda u: ("_part" not in u, u))

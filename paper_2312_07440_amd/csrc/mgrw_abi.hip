@@ -238,6 +238,7 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     p->t0 = p->t1 = nullptr;
     p->timed = 0;
     p->colour_mfma = 0;
+    p->hp = nullptr;
     *out = p;
     return MGRW_OK;
 }
@@ -361,6 +362,7 @@ void mgrw_destroy_process(mgrw_process* p) {
         (void)hipEventDestroy(p->t1);
     }
     mgrw::surrogate_destroy(p->sur);
+    mgrw::host_pipeline_destroy(p->hp);
     delete p;
 }
 

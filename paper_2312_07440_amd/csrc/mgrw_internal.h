@@ -10,6 +10,8 @@
 namespace mgrw {
 struct surrogate;                       // MLP state (mgrw_mlp.hip)
 void surrogate_destroy(surrogate* s);
+struct host_pipeline;                   // streams and staging of mgrw_reweight_host (mgrw_stream.hip)
+void host_pipeline_destroy(host_pipeline* h);
 mgrw_status set_error(mgrw_status code, const std::string& msg);
 }  // namespace mgrw
 
@@ -25,4 +27,5 @@ struct mgrw_process {
     hipEvent_t t0, t1;                  // amplitude-kernel timestamps (timing option), else null
     int timed;                          // a launch has recorded t0/t1
     int colour_mfma;                    // g g -> t tbar g g g: colour sum on the matrix cores
+    mgrw::host_pipeline* hp;            // null until mgrw_reweight_host is first called
 };

@@ -124,3 +124,16 @@ def test_surrogate_checkpoint_errors(L, tmp_path):
     assert L.mgrw_surrogate_load(None, str(tmp_path / "magic.sur").encode()) == bd.ERR_ARG
     assert L.mgrw_surrogate_load(p._h, None) == bd.ERR_ARG
     p.close()
+
+
+def test_host_reweight_argument_errors(L):
+    """mgrw_reweight_host checks its arguments before touching the device."""
+    p = bd.Process("gg_ttg", "mixed")
+    assert L.mgrw_reweight_host(p._h, None, None, 10, None, None, 0) == bd.ERR_STATE   # no points
+    p.set_params([{"kappa_ttg": 1.1}])
+    assert L.mgrw_reweight_host(p._h, None, None, -1, None, None, 0) == bd.ERR_ARG
+    assert L.mgrw_reweight_host(p._h, None, None, 10, None, None, -5) == bd.ERR_ARG
+    assert L.mgrw_reweight_host(p._h, None, None, 10, None, None, 0) == bd.ERR_ARG     # null arrays
+    assert L.mgrw_reweight_host(p._h, None, None, 0, None, None, 0) == bd.OK           # nothing to do
+    assert L.mgrw_reweight_host(None, None, None, 0, None, None, 0) == bd.ERR_ARG
+    p.close()
