@@ -79,6 +79,17 @@ MGRW_HD void kpoly_colour(const cx<T>* J, double* B) {
         // other (no single power is gauge invariant), so the colour products
         // of float amplitudes are accumulated in double.
         using TA = typename kpoly_acc<T>::type;
+        if (pb == 0) {
+            // B_00 alone: the symmetric quadratic form, half the products of
+            // CF J_0 followed by a dot product
+            cx<TA> Jd[Proc::K];
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+#endif
+            for (int i = 0; i < Proc::K; ++i) Jd[i] = {TA(J[i].re), TA(J[i].im)};
+            B[0] += double(Proc::template colour_sum<TA>(Jd));
+            continue;
+        }
         cx<TA> Z[Proc::K];
         Proc::template colour_matvec<TA, T>(J + pb * Proc::K, Z);
 #if defined(__HIP_DEVICE_COMPILE__)
