@@ -27,7 +27,7 @@ ALPHA0 = 1 / 132.5
 # HBM traffic of the exact amplitude kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (copy-calibrated; see profiles/), valid only for the sources that
 # kernel is built from: keyed by a fingerprint of those sources.
-MEASURED_TRAFFIC = {("gg_ttgg", "mixed", "74b35e524b4bf994"): 1955.7}   # bytes per event per launch
+MEASURED_TRAFFIC = {("gg_ttgg", "mixed", "fc76df9a4ca7ced9"): 1788.6}   # bytes per event per launch
 WAVE_SECTION = ("// ------------------------------------------------ one event per wave",
                 "// ------------------------------------------------ kappa-polynomial kernels")
 
