@@ -196,7 +196,8 @@ mgrw_status mgrw_set_option(mgrw_process *p, int option, int64_t value);
 mgrw_status mgrw_kernel_time_ms(mgrw_process *p, double *ms);
 
 /* Release the handle (NULL is ignored).  Work already launched with it is
- * unaffected: its parameters travelled with the launch. */
+ * unaffected: its parameters travelled with the launch.  The streams and
+ * staging buffers of mgrw_reweight_host are released after their work ends. */
 void mgrw_destroy_process(mgrw_process *p);
 
 /* One reweight over a sample that mixes processes, such as the Born and
