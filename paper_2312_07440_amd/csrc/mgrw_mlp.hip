@@ -975,14 +975,18 @@ mgrw_status mgrw_reweight_surrogate(mgrw_process* p, const double* mom, const do
 
     // 1. surrogate weights for every (event, point), in chunks of events: the
     // event features once per event, then the fused network over its P rows
-    const int64_t chunk_ev = std::max<int64_t>(1, (int64_t(1) << 20) / P);
-    HIPCHK(ensure_rows(s, ((chunk_ev * P + 63) / 64) * 64));
+    // (only the per-event features need a buffer: the activations stay in LDS)
+    const int64_t chunk_ev = std::min<int64_t>(n_events, std::max<int64_t>(1, (int64_t(1) << 20) / P));
+    dbuf<uint16_t> xev;
+    dbuf<float> kdev;
+    HIPCHK(xev.alloc(size_t(chunk_ev) * K0));
+    HIPCHK(kdev.alloc(size_t(chunk_ev)));
     for (int64_t e0 = 0; e0 < n_events; e0 += chunk_ev) {
         const int64_t ne = std::min(chunk_ev, n_events - e0);
         const int64_t rows = ne * P;
         hipLaunchKernelGGL(features_kernel, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, mom, n_ext,
-                           n_events, e0, 1, kap.p, ne, s->x0.p, s->kd.p);
-        hipLaunchKernelGGL(mlp_infer_kernel, dim3(unsigned((rows + FR - 1) / FR)), dim3(256), 0, st, s->x0.p, P,
+                           n_events, e0, 1, kap.p, ne, xev.p, kdev.p);
+        hipLaunchKernelGGL(mlp_infer_kernel, dim3(unsigned((rows + FR - 1) / FR)), dim3(256), 0, st, xev.p, P,
                            kap.p, int(rows), e0, n_events, s->pbf.p, s->par.p, w_in, w_out);
     }
     HIPCHK(hipGetLastError());
