@@ -552,8 +552,12 @@ struct mfma_colour : std::false_type {};
 template <class P>
 struct mfma_colour<P, std::void_t<decltype(P::MFMA_COLOUR)>> : std::bool_constant<P::MFMA_COLOUR> {};
 
+#ifndef MGRW_PART_WPE
+#define MGRW_PART_WPE 1
+#endif
+
 template <class Proc, typename T, int C, bool STORE_LAST>
-__global__ void __launch_bounds__(kBlock, 1)
+__global__ void __launch_bounds__(kBlock, MGRW_PART_WPE)
 qcd_part_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t nb, T* __restrict__ jbuf,
                 const double* __restrict__ w_in, int64_t n, qcd_launch a, double* __restrict__ out,
                 double* __restrict__ me0_out) {

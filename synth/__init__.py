@@ -13,6 +13,7 @@ from .phase_space import (  # noqa: F401
     ProcessSpec,
     generate_events,
     kappa_points,
+    uneven_batches,
     alpha_points,
     ee_mumu,
     gg_tt,

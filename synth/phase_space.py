@@ -215,6 +215,21 @@ def generate_events(proc, n, first_event=0, seed=None):
                          first_event=first_event)
 
 
+def uneven_batches(proc, n=None, lo=65536, hi=262144, seed=None):
+    """Seeded batch sizes B_k ~ U{lo..hi} covering `n` events (the workload's
+    full sample by default); the last batch is the remainder and may be
+    smaller than `lo`."""
+    spec = PROCESSES[proc]
+    n = spec.n_events if n is None else n
+    seed = spec.seed if seed is None else seed
+    sizes, b = [], 0
+    while sum(sizes) < n:
+        s = int(lo + uniform(seed, STREAM_BATCH, b, 0) * (hi - lo + 1))
+        sizes.append(min(s, n - sum(sizes)))
+        b += 1
+    return sizes
+
+
 def alpha_points(n_points=16, seed=6000, alpha0=1 / 132.5, lo=0.5, hi=1.5):
     """`n_points` iid draws of the electromagnetic coupling, uniform in
     [lo, hi] * alpha0 (a random non-zero value per reweight iteration)."""

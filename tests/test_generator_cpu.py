@@ -45,7 +45,7 @@ def test_colour_coefficients_are_signs(ng):
         assert all(c in (1, -1) for c in col.values())
 
 
-@pytest.mark.parametrize("ng", [2, 3, 4])
+@pytest.mark.parametrize("ng", [2, 3, 4, 5])
 def test_generator_colour_matrix_matches_oracle(ng):
     assert P.colour_matrix_loops(ng) == oracle.colour_matrix(ng)
 

@@ -297,8 +297,8 @@ def test_gg_ttggg_full_configuration_uneven_batches(torch_dev):
     seeded uneven batches of 65 536..262 144 events (the last one the
     remainder), 16 points; sampled events against the oracle."""
     import paper_2312_07440_amd as mg
-    from synth.rng import uniform
-    from synth.phase_space import PROCESSES, STREAM_BATCH
+    from synth import uneven_batches
+    from synth.phase_space import PROCESSES
     torch = torch_dev
     spec = PROCESSES["gg_ttggg"]
     n = spec.n_events
@@ -307,11 +307,7 @@ def test_gg_ttggg_full_configuration_uneven_batches(torch_dev):
     kap = kappa_points(16)
     p = mg.Process("gg_ttggg", "mixed")
     p.set_params([{"kappa_ttg": float(k)} for k in kap])
-    sizes, b = [], 0
-    while sum(sizes) < n:
-        s = int(65536 + uniform(spec.seed, STREAM_BATCH, b, 0) * (262144 - 65536 + 1))
-        sizes.append(min(s, n - sum(sizes)))
-        b += 1
+    sizes = uneven_batches("gg_ttggg", n)
     out = np.empty((16, n))
     e0 = 0
     for s in sizes:

@@ -410,3 +410,24 @@ def test_reweight_definition():
     assert out[0, 0] == 6.0 and out[0, 2] == -4.0 and out[0, 3] == 0.125
     assert out[1, 0] == 1.5 and out[1, 2] == -1.0 and out[1, 3] == 1.0
     assert np.array_equal(oracle.reweight(me)[0, [0, 2, 3]], [2.0, 2.0, 0.25])
+
+
+def test_colour_matrix_vs_gell_mann_sum_sampled_n5():
+    """Entries of the 120 x 120 matrix of five gluons against explicit sums
+    over all 8^5 adjoint colour assignments of Tr(T^s T^r^+)."""
+    words = oracle.orderings(5)
+    cf = oracle.colour_matrix_float(5)
+    rng = np.random.default_rng(11)
+    pairs = [(0, 0), (0, 119), (7, 58)] + [(int(rng.integers(120)), int(rng.integers(120))) for _ in range(5)]
+    Tn = np.array(T)
+    cols = np.array(list(itertools.product(range(8), repeat=5)))      # (32768, 5)
+
+    def chain(w):
+        x = np.broadcast_to(np.eye(3, dtype=complex), (len(cols), 3, 3))
+        for k in w:
+            x = x @ Tn[cols[:, k]]
+        return x
+
+    for s, r in pairs:
+        val = np.sum(chain(words[s]) * chain(words[r]).conj())
+        assert abs(val.imag) < 1e-9 and abs(val.real - cf[s, r]) < 1e-9, (s, r, val, cf[s, r])
