@@ -47,6 +47,46 @@ def kernel_fingerprint(proc="gg_ttgg"):
     return h.hexdigest()[:16]
 
 
+# Executed FP32 flops of the amplitude kernel over the counted (algorithmic)
+# flops of the events it evaluates, from SQ_INSTS_VALU_{FMA,MUL,ADD}_F32
+# (profiles/), for the same kernel sources as MEASURED_TRAFFIC.
+MEASURED_EXEC_RATIO = {("gg_ttgg", "mixed", "fc76df9a4ca7ced9"): 0.885}
+RESCUE_TAU = 3e-3   # the library's default FP64 re-evaluation threshold (mixed precision)
+
+
+def rescued_events(mom_np, tau=RESCUE_TAU):
+    """Events the mixed-precision call leaves to its FP64 re-evaluation: a
+    gluon pair other than the two beams with |2 p_i.p_j| / s below tau (the
+    library's criterion, evaluated here in float64)."""
+    n_ext = mom_np.shape[0]
+    p = mom_np
+    s = (p[0, 0] + p[1, 0]) ** 2 - ((p[0, 1:] + p[1, 1:]) ** 2).sum(axis=0)
+    glu = [0, 1] + list(range(4, n_ext))
+    bad = np.zeros(p.shape[2], dtype=bool)
+    for a in range(len(glu)):
+        for b in range(a + 1, len(glu)):
+            i, j = glu[a], glu[b]
+            if (i, j) == (0, 1):
+                continue
+            d = p[i, 0] * p[j, 0] - p[i, 1] * p[j, 1] - p[i, 2] * p[j, 2] - p[i, 3] * p[j, 3]
+            bad |= np.abs(2.0 * d) < tau * s
+    return int(bad.sum())
+
+
+def host_info():
+    """CPU model and logical CPUs of the host, and the CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc_online": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0))}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -73,6 +113,7 @@ def cpu_baseline(proc, ng, mom_np, kap, gpu_out, sample, points_per_event):
         return w, time.perf_counter() - t0
 
     cores = oracle.max_threads()
+    info = host_info()
     w, dt = run(sample)
     err = np.abs(gpu_out[:, :sample] / w - 1)
     # one thread on a sixteenth of the sample
@@ -84,6 +125,7 @@ def cpu_baseline(proc, ng, mom_np, kap, gpu_out, sample, points_per_event):
             "kind": "oracle",
             "sample": f"first {sample} events of the same sample, base + {len(kap)} points, FP64 oracle "
                       f"({dt:.1f} s wall)",
+            "host": info, "build": " ".join(["gcc"] + oracle.CFLAGS),
             "single_thread": {"value": s1 * points_per_event / dt1, "events": s1, "seconds": dt1}}, \
         float(err.max()), float(np.median(err))
 
@@ -122,7 +164,7 @@ def surrogate_leg(args, proc, mom, exact_out, kap, torch, generate_events):
             "timing": "host wall clock per call (the call synchronises once for the audit statistics)"}
 
 
-def kpoly_leg(args, proc, mom, exact_out, stream, torch):
+def kpoly_leg(args, proc, mom, exact_out, stream, torch, n_eval):
     """The kappa-polynomial exact variant on the same batch and points: timed
     with device events like the main leg, checked against its weights."""
     kout = torch.empty_like(exact_out)
@@ -143,7 +185,7 @@ def kpoly_leg(args, proc, mom, exact_out, stream, torch):
     f = json.load(open(os.path.join(HERE, "paper_2312_07440_amd", "csrc", "gen", "flops.json")))[args.proc]
     fpe = (f["evaluated_helicities"] * f["per_helicity_flops"] if args.proc == "ee_5a"
            else proc.n_hel * f["kpoly_per_helicity_flops"])
-    achieved = fpe * args.n / (kms * 1e-3) / 1e12
+    achieved = fpe * n_eval / (kms * 1e-3) / 1e12   # the events its kernel evaluates
     peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
     diff = float(torch.abs(kout / exact_out - 1.0).max())
     return {"value": args.n * args.points / (ms * 1e-3), "unit": "events*points/s", "ms_per_step": ms,
@@ -319,8 +361,14 @@ def main():
 
     n_total_points = args.points + 1
     fpe, fcounts = flops_per_event(args.proc, n_total_points, proc.n_hel)
-    achieved = fpe * args.n / (kms * 1e-3) / 1e12
+    # the amplitude kernel skips the events left to the FP64 re-evaluation
+    # (outside the timed interval): count only the events it evaluates
+    rescue = args.prec == "mixed" and args.proc != "ee_5a" and ng >= 3
+    n_rescued = rescued_events(mom_np) if rescue else 0
+    n_eval = args.n - n_rescued
+    achieved = fpe * n_eval / (kms * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
+    exec_ratio = MEASURED_EXEC_RATIO.get((args.proc, args.prec, kernel_fingerprint(args.proc)))
     value = args.n * args.points / (ms * 1e-3)
     tb = MEASURED_TRAFFIC.get((args.proc, args.prec, kernel_fingerprint(args.proc)))
     traffic = None if tb is None else tb * args.n
@@ -345,15 +393,21 @@ def main():
                    "precision": args.prec, "path": "exact"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "amplitude kernel (one event per wave)", "kernel_ms": kms,
-                     "flops_per_event": fpe, "per_helicity_flops": fcounts["per_helicity_flops"]},
+                     "kernel": ("amplitude kernels (split program parts)" if args.proc == "gg_ttggg"
+                                else "amplitude kernel (one event per wave)"),
+                     "kernel_ms": kms,
+                     "flops_per_event": fpe, "per_helicity_flops": fcounts["per_helicity_flops"],
+                     "events_evaluated": n_eval, "events_rescued_fp64": n_rescued,
+                     "counts": "algorithmic flops of the generated program (currents rebuilt per closing "
+                               "group included) x the events the timed kernel evaluates",
+                     "frac_executed": None if exec_ratio is None else exec_ratio * achieved / peak},
     }
     if not args.no_end_to_end:
         log("end-to-end (host buffers)")
         res["end_to_end"] = end_to_end_leg(args, proc, mom_np, mom, out, stream, torch)
     if not args.no_kpoly and args.proc in ("gg_tt", "gg_ttg", "gg_ttgg", "ee_5a"):
         log("kappa-polynomial variant")
-        res["kpoly"] = kpoly_leg(args, proc, mom, out, stream, torch)
+        res["kpoly"] = kpoly_leg(args, proc, mom, out, stream, torch, n_eval)
     if not args.no_surrogate and args.proc != "ee_5a":
         res["surrogate"] = surrogate_leg(args, proc, mom, out, kap, torch, generate_events)
     if not args.no_cpu_baseline:

@@ -164,7 +164,7 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
  * configurations on the lanes; processes with a multiple of 64 helicity
  * configurations only).  Results agree to rounding.
  *
- * MGRW_OPT_RESCUE_PPM (mixed precision, g g -> t tbar + 0..2 g): events in
+ * MGRW_OPT_RESCUE_PPM (mixed precision, g g -> t tbar + 0..3 g): events in
  * which a gluon pair other than the two beams has |2 p_i.p_j| / s below
  * value * 1e-6 are evaluated a second time in FP64 and their results
  * replaced.  There the diagrams cancel strongly and single-precision
@@ -261,7 +261,9 @@ void mgrw_lhe_close(mgrw_lhe *h);
  * the prediction is exact at kappa = 1.  Surrogate weights W~' = W exp(yhat).
  * A random audit subset of events is evaluated exactly (eq. (3)) and serves
  * as a control variate for the sums of weights.  QCD processes only; the
- * points must differ from the base only in kappa_ttg.
+ * base point must have kappa_ttg = 1 (where the prediction is exact) and the
+ * points must differ from it only in kappa_ttg (MGRW_ERR_UNSUPPORTED
+ * otherwise).
  *
  * Parameters (float32, MGRW_SURROGATE_N_PARAMS values) in this order:
  * W1[256][64] (input columns 53..63 unused, zero), b1[256], W2[256][256],
@@ -310,10 +312,16 @@ mgrw_status mgrw_surrogate_train_samples(mgrw_process *p, const float *x, const 
  * [n_points][5], may be NULL) receives per point: the control-variate estimate
  * of sum_e W'_e (surrogate sum + (exact - surrogate) summed over the audit /
  * audit_fraction), the surrogate sum, the audited mean |W~'/W' - 1|, its
- * standard error, and the number of audited events.  If the audited mean
- * error of any point exceeds max_audit_error the whole batch is recomputed
- * exactly and *fell_back (may be NULL) is set to 1.  Synchronises once.
- * Errors: as mgrw_reweight; MGRW_ERR_STATE if no surrogate is trained. */
+ * standard error, and the number of audited events.  The mean and its error
+ * are taken over the audited events with a finite, non-zero exact weight
+ * (a zero input weight makes both weights zero; |M|^2 = 0 at the base makes
+ * the exact one NaN, eq. (3)); with none of those the mean is 0.  If the
+ * audited mean error of any point exceeds max_audit_error (or is NaN) the
+ * whole batch is recomputed exactly and *fell_back (may be NULL) is set to 1.
+ * Scratch memory is allocated and freed in the stream's order; the call
+ * synchronises the stream once, to read the audit statistics.
+ * Errors: as mgrw_reweight (host pointers among mom, w_in, w_out:
+ * MGRW_ERR_ARG); MGRW_ERR_STATE if no surrogate is trained. */
 mgrw_status mgrw_reweight_surrogate(mgrw_process *p, const double *mom, const double *w_in, int64_t n_events,
                                     double audit_fraction, uint64_t seed, double max_audit_error,
                                     double *w_out, double *audit_stats, int *fell_back, void *stream);

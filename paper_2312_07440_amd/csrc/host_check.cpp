@@ -60,6 +60,42 @@ void me_events_kpoly(const double* mom, int64_t n, double mt, const mgrw::qcd_po
     }
 }
 
+// |M|^2 through the double-precision cut of a split program: every (chunk,
+// flow range) function adds its terms to its range of J, then the colour sum.
+template <class Proc, int Q>
+void fr_all(const typename Proc::template ext<double>& w, const typename Proc::template kin<double>& k,
+            const typename Proc::template coup<double>& c, mgrw::cx<double>* J) {
+    if constexpr (Q < Proc::NCHUNK64 * Proc::NFR) {
+        constexpr int C = Q / Proc::NFR, R = Q % Proc::NFR;
+        Proc::template amplitude_fr<C, R, double>(w, k, c, J + R * Proc::KR);
+        fr_all<Proc, Q + 1>(w, k, c, J);
+    }
+}
+
+template <class Proc>
+void me_events_split(const double* mom, int64_t n, double mt, const mgrw::qcd_point* pts, int npts, double* me) {
+    for (int64_t e = 0; e < n; ++e) {
+        double p[Proc::NEXT][4];
+        for (int i = 0; i < Proc::NEXT; ++i)
+            for (int m = 0; m < 4; ++m) p[i][m] = mom[(int64_t(i) * 4 + m) * n + e];
+        mgrw::qcd_event<Proc, double> ev;
+        ev.setup(p, mt);
+        for (int kp = 0; kp < npts; ++kp) {
+            typename Proc::template coup<double> c = {pts[kp].gs, pts[kp].gs2, pts[kp].gk};
+            double acc = 0.0;
+            for (int h = 0; h < Proc::NHEL; ++h) {
+                typename Proc::template ext<double> w;
+                Proc::template external<double>(ev.b, h, w);
+                mgrw::cx<double> J[Proc::K];
+                for (int f = 0; f < Proc::K; ++f) J[f] = {0.0, 0.0};
+                fr_all<Proc, 0>(w, ev.k, c, J);
+                acc += Proc::colour_sum(J);
+            }
+            me[int64_t(kp) * n + e] = acc * Proc::NORM;
+        }
+    }
+}
+
 // add + mul of one helicity of the kappa-polynomial evaluation
 template <class Proc>
 long long count_kpoly() {
@@ -139,6 +175,20 @@ int mgrw_host_qcd_me_kpoly(int ng, const double* mom, int64_t n, double mt, cons
         case 4: me_events_kpoly<mgrw::gg_ttgg, double>(mom, n, mt, pts, npts, me); return 0;
         default: return -2;
     }
+}
+
+// g g -> t tbar g g g through its double-precision (chunk, flow range) cut.
+int mgrw_host_qcd_me_split(int ng, const double* mom, int64_t n, double mt, const double* pts_gs_gk, int npts,
+                           double* me) {
+    if (npts < 1 || npts > 64 || n < 0) return -1;
+    if (ng != 5) return -2;
+    mgrw::qcd_point pts[64];
+    for (int k = 0; k < npts; ++k) {
+        double gs = pts_gs_gk[2 * k], kap = pts_gs_gk[2 * k + 1];
+        pts[k] = {gs, gs * gs, gs * kap};
+    }
+    me_events_split<mgrw::gg_ttggg>(mom, n, mt, pts, npts, me);
+    return 0;
 }
 
 long long mgrw_host_kpoly_flops(int ng) {

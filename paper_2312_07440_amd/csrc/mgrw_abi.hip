@@ -1,11 +1,16 @@
-// libmgrw: HIP kernels for gfx950 and the C ABI declared in include/mgrw.h.
+// libmgrw: the C ABI declared in include/mgrw.h (argument checks, parameter
+// points, dispatch to the per-process launchers) and the e+ e- -> mu+ mu-
+// kernel.
 //
-// One event per lane.  Each lane reads its event's momenta once (structure of
-// arrays: consecutive lanes read consecutive doubles of each component),
-// builds the helicity-independent kinematics in double, then evaluates the
-// amplitude program at the base point and at every new parameter point and
-// writes the reweighted weights (Sec. 3.2, steps 3-8; eq. (3)).  The helicity
-// loop is wave-uniform, so lanes never diverge inside the diagram chains.
+// Every launch reads each event's momenta once (structure of arrays: lanes
+// read consecutive doubles of each component), builds the helicity-
+// independent kinematics in double, then evaluates the amplitude program at
+// the base point and at every new parameter point and writes the reweighted
+// weights (Sec. 3.2, steps 3-8; eq. (3)).  QCD processes whose number of
+// helicity configurations is a multiple of 64 run one event per 64-lane wave
+// with the configurations on the lanes (mgrw_kernels.h); the others one event
+// per lane with a wave-uniform helicity loop, so lanes never diverge inside
+// the diagram chains.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -122,22 +127,6 @@ mgrw::ew_point ew_point_of(const mgrw_params& q) {
     return {e2, e2 / (q.sw2 * (1.0 - q.sw2)), -0.5 + q.sw2, q.sw2, q.mz * q.mz, q.mz * q.wz};
 }
 
-mgrw_status check_device_ptr(const void* ptr, const char* what, bool allow_null) {
-    if (!ptr) {
-        if (allow_null) return MGRW_OK;
-        return fail(MGRW_ERR_ARG, std::string(what) + " is NULL");
-    }
-    hipPointerAttribute_t attr;
-    hipError_t err = hipPointerGetAttributes(&attr, ptr);
-    if (err != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(MGRW_ERR_ARG, std::string(what) + " is not a HIP allocation");
-    }
-    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
-        return fail(MGRW_ERR_ARG, std::string(what) + " is not device memory");
-    return MGRW_OK;
-}
-
 mgrw_status launched(hipError_t err) {
     if (err != hipSuccess) return fail(MGRW_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(err));
     return MGRW_OK;
@@ -222,8 +211,6 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     if (info_of(proc).n_ext == 0) return fail(MGRW_ERR_UNSUPPORTED, "process not built into this library");
     if (proc == MGRW_EE_MUMU && prec != MGRW_FP64)
         return fail(MGRW_ERR_UNSUPPORTED, "e+e- -> mu+mu- is built in FP64 only");
-    if (proc == MGRW_GG_TTGGG && prec != MGRW_MIXED)
-        return fail(MGRW_ERR_UNSUPPORTED, "g g -> t tbar g g g is built in mixed precision only");
     mgrw_status st = check_params(proc, *base, "base");
     if (st != MGRW_OK) return st;
     mgrw_process* p = new (std::nothrow) mgrw_process;
@@ -233,7 +220,7 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     p->base = *base;
     p->n_points = 0;
     p->mapping = MGRW_MAP_AUTO;
-    p->rescue_tau = (prec == MGRW_MIXED && proc >= MGRW_GG_TT && proc <= MGRW_GG_TTGG) ? 3e-3 : 0.0;
+    p->rescue_tau = (prec == MGRW_MIXED && proc >= MGRW_GG_TT && proc <= MGRW_GG_TTGGG) ? 3e-3 : 0.0;
     p->sur = nullptr;
     p->t0 = p->t1 = nullptr;
     p->timed = 0;
@@ -305,8 +292,8 @@ mgrw_status mgrw_set_option(mgrw_process* p, int option, int64_t value) {
     if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
     if (option == MGRW_OPT_RESCUE_PPM) {
         if (value < 0 || value > 1000000) return fail(MGRW_ERR_ARG, "rescue threshold must be 0..1000000 ppm");
-        if (value != 0 && (p->prec != MGRW_MIXED || p->proc < MGRW_GG_TT || p->proc > MGRW_GG_TTGG))
-            return fail(MGRW_ERR_UNSUPPORTED, "FP64 rescue: mixed precision g g -> t tbar + 0..2 g only");
+        if (value != 0 && (p->prec != MGRW_MIXED || p->proc < MGRW_GG_TT || p->proc > MGRW_GG_TTGGG))
+            return fail(MGRW_ERR_UNSUPPORTED, "FP64 rescue: mixed precision g g -> t tbar + 0..3 g only");
         p->rescue_tau = double(value) * 1e-6;
         return MGRW_OK;
     }
@@ -371,3 +358,19 @@ const char* mgrw_last_error(void) { return g_last_error.c_str(); }
 }  // extern "C"
 
 mgrw_status mgrw::set_error(mgrw_status code, const std::string& msg) { return fail(code, msg); }
+
+mgrw_status mgrw::check_device_ptr(const void* ptr, const char* what, bool allow_null) {
+    if (!ptr) {
+        if (allow_null) return MGRW_OK;
+        return fail(MGRW_ERR_ARG, std::string(what) + " is NULL");
+    }
+    hipPointerAttribute_t attr;
+    hipError_t err = hipPointerGetAttributes(&attr, ptr);
+    if (err != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MGRW_ERR_ARG, std::string(what) + " is not a HIP allocation");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(MGRW_ERR_ARG, std::string(what) + " is not device memory");
+    return MGRW_OK;
+}

@@ -13,6 +13,9 @@ void surrogate_destroy(surrogate* s);
 struct host_pipeline;                   // streams and staging of mgrw_reweight_host (mgrw_stream.hip)
 void host_pipeline_destroy(host_pipeline* h);
 mgrw_status set_error(mgrw_status code, const std::string& msg);
+// MGRW_OK if ptr is device (or managed) memory, or NULL with allow_null;
+// else MGRW_ERR_ARG naming `what`.
+mgrw_status check_device_ptr(const void* ptr, const char* what, bool allow_null);
 }  // namespace mgrw
 
 struct mgrw_process {

@@ -567,6 +567,7 @@ qcd_part_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
     const int64_t el = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (el >= nb) return;   // whole wave; no barriers below
     const int64_t e = e0 + el;
+    if (ev[e].skip) return;   // left to the FP64 re-evaluation
     const int lane = threadIdx.x & 63;
     const typename Proc::template kin<T>& k = ev[e].k;
     const typename Proc::template basis<T>& b = ev[e].b;
@@ -766,8 +767,259 @@ hipError_t launch_colour_mfma(const float* jbuf, int64_t e0, int64_t nb, const d
     }
 }
 
-// Events per batch of the split programs (bounds the HBM buffer for J).
+// ------------------------------ double-precision instance of the split programs
+//
+// In double precision the 120 colour-flow amplitudes of g g -> t tbar g g g
+// alone would take 480 registers per lane.  The generated program is
+// therefore also cut by colour flow: amplitude_fr<C, R> holds the diagrams of
+// chunk C of the closing groups that contribute to flow range R (KR flows),
+// so only KR amplitudes are live at a time; diagrams with terms in several
+// ranges are evaluated once per range.  Kernel (C, R) runs it for a batch of
+// events, one event per wave with the helicity configurations on the lanes,
+// and passes the range's amplitudes through HBM ([event][point][component]
+// [helicity], as the single-precision parts do); qcd_colour64_kernel then
+// forms the colour sum from HBM, the helicity sum and the weights.
+//
+// The same pipeline re-evaluates the ill-conditioned events of the
+// single-precision pass: slots are then positions in the list of those
+// events (count on the device), and slots beyond the count exit at once.
+
+// Per-event data of one slot: event e itself, or list[slot].
+template <class Proc>
+__global__ void __launch_bounds__(kBlock)
+qcd_setup64_kernel(const double* __restrict__ mom, int64_t n, double mt, const int64_t* __restrict__ list,
+                   const unsigned long long* __restrict__ count, int64_t slots,
+                   event_data<Proc, double>* __restrict__ ev) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= slots || (count && i >= int64_t(count[0]))) return;
+    const int64_t e = list ? list[i] : i;
+    double p[Proc::NEXT][4];
+    load_event<Proc::NEXT>(mom, n, e, p);
+    Proc::kinematics(p, mt, ev[i].k);
+    Proc::external_basis(p, mt, ev[i].b);
+    ev[i].skip = 0;
+}
+
+template <class Proc, int C, int R>
+__global__ void __launch_bounds__(kBlock, 1)
+qcd_fr_kernel(const event_data<Proc, double>* __restrict__ ev, const unsigned long long* __restrict__ count,
+              int64_t e0, int64_t nb, double* __restrict__ jbuf, qcd_launch a) {
+    constexpr int NH = Proc::NHEL, K2 = 2 * Proc::K, KR = Proc::KR;
+    static_assert(NH % 64 == 0, "helicity configurations must fill whole waves");
+    const int64_t el = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (el >= nb) return;   // whole wave; no barriers below
+    const int64_t i = e0 + el;
+    if (count && i >= int64_t(count[0])) return;
+    const int lane = threadIdx.x & 63;
+    const typename Proc::template kin<double>& k = ev[i].k;
+    const typename Proc::template basis<double>& b = ev[i].b;
+#pragma unroll 1
+    for (int kp = 0; kp < a.npts; ++kp) {
+        const qcd_point pt = a.pts[kp];
+        typename Proc::template coup<double> c = {pt.gs, pt.gs2, pt.gk};
+#pragma unroll 1
+        for (int hc = 0; hc < NH; hc += 64) {
+            __asm__ volatile("" ::: "memory");
+            __shared__ lds_slot<typename Proc::template ext<double>> wfs[kBlock];
+            typename Proc::template ext<double>& wf = wfs[threadIdx.x].v;   // own slot
+            Proc::template external<double>(b, hc + lane, wf);
+            double* jp = jbuf + (el * a.npts + kp) * int64_t(K2) * NH + int64_t(2 * R * KR) * NH + hc + lane;
+            cx<double> J[KR];
+            if constexpr (C == 0) {
+#pragma unroll
+                for (int f = 0; f < KR; ++f) J[f] = {0.0, 0.0};
+            } else {
+#pragma unroll
+                for (int f = 0; f < KR; ++f) J[f] = {jp[(2 * f) * NH], jp[(2 * f + 1) * NH]};
+            }
+            Proc::template amplitude_fr<C, R>(wf, k, c, J);
+#pragma unroll
+            for (int f = 0; f < KR; ++f) {
+                jp[(2 * f) * NH] = J[f].re;
+                jp[(2 * f + 1) * NH] = J[f].im;
+            }
+        }
+    }
+}
+
+// Flows per block of the streamed colour sum (z = CF J for BS rows at a time).
+constexpr int kColourBlock = 40;
+
+// sum_h J_h^+ CF J_h from the amplitudes in HBM: per lane (helicity) and block
+// of kColourBlock rows, z_i = sum_t CF[t][i] J_t with J_t streamed from memory
+// (CF symmetric, row t of the table contiguous in i, read through the scalar
+// cache), then the block's Re(J_i^* z_i); helicity sum by wave reduction.
+template <class Proc>
+__global__ void __launch_bounds__(kBlock)
+qcd_colour64_kernel(const double* __restrict__ jbuf, const int64_t* __restrict__ list,
+                    const unsigned long long* __restrict__ count, int64_t e0, int64_t nb,
+                    const double* __restrict__ w_in, int64_t n, qcd_launch a, double* __restrict__ out,
+                    double* __restrict__ me0_out) {
+    constexpr int K = Proc::K, NH = Proc::NHEL, BS = kColourBlock;
+    static_assert(K % BS == 0, "colour blocks");
+    const int64_t el = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (el >= nb) return;   // whole wave
+    if (count && e0 + el >= int64_t(count[0])) return;
+    const int64_t e = list ? list[e0 + el] : e0 + el;
+    const int lane = threadIdx.x & 63;
+    const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
+    double me0 = 0.0;
+#pragma unroll 1
+    for (int kp = 0; kp < a.npts; ++kp) {
+        double acc = 0.0;
+#pragma unroll 1
+        for (int hc = 0; hc < NH; hc += 64) {
+            const double* X = jbuf + (el * a.npts + kp) * int64_t(2 * K) * NH + hc + lane;
+#pragma unroll 1
+            for (int a0 = 0; a0 < K; a0 += BS) {
+                double zr[BS], zi[BS];
+#pragma unroll
+                for (int q = 0; q < BS; ++q) zr[q] = zi[q] = 0.0;
+#pragma unroll 2
+                for (int t = 0; t < K; ++t) {
+                    const double jr = X[(2 * t) * NH], ji = X[(2 * t + 1) * NH];
+                    const double* cf = Proc::CF_DBL + t * K + a0;
+#pragma unroll
+                    for (int q = 0; q < BS; ++q) {
+                        zr[q] = fma(cf[q], jr, zr[q]);
+                        zi[q] = fma(cf[q], ji, zi[q]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < BS; ++q)
+                    acc += zr[q] * X[(2 * (a0 + q)) * NH] + zi[q] * X[(2 * (a0 + q) + 1) * NH];
+            }
+        }
+        const double me = wave_sum(acc) * Proc::NORM;
+        if (kp == 0) {
+            me0 = me;
+            if (lane == 0) {
+                if (a.mode == 1)
+                    out[e] = me;
+                else if (me0_out)
+                    me0_out[e] = me;
+            }
+        } else if (lane == 0) {
+            out[int64_t(kp - 1) * n + e] = reweighted(w, me, me0);
+        }
+    }
+}
+
+template <class Proc, int C, int R>
+hipError_t launch_fr(const event_data<Proc, double>* ev, const unsigned long long* count, int64_t e0, int64_t nb,
+                     double* jbuf, const qcd_launch& a, hipStream_t s) {
+    const dim3 grid(unsigned((nb + kBlock / 64 - 1) / (kBlock / 64)));
+    hipLaunchKernelGGL((qcd_fr_kernel<Proc, C, R>), grid, dim3(kBlock), 0, s, ev, count, e0, nb, jbuf, a);
+    return hipGetLastError();
+}
+
+// Kernel launchers of a split program, one translation unit each.
+template <class Proc>
+struct split_launchers {
+    using part_fn = hipError_t (*)(const event_data<Proc, float>*, int64_t, int64_t, float*, const double*, int64_t,
+                                   const qcd_launch&, double*, double*, hipStream_t);
+    using fr_fn = hipError_t (*)(const event_data<Proc, double>*, const unsigned long long*, int64_t, int64_t,
+                                 double*, const qcd_launch&, hipStream_t);
+    part_fn part[Proc::NCHUNK];
+    fr_fn fr[Proc::NCHUNK64 * Proc::NFR];
+};
+
+// Events per batch of the split programs: the buffer that carries J between
+// the parts holds batch x points x 2K x NHEL values of T, about 16 GiB at most.
 constexpr int64_t kPartBatch = 8192;
+constexpr size_t kJBufBytes = size_t(16) << 30;
+template <class Proc, typename T>
+int64_t part_batch(int64_t n, int npts) {
+    const size_t per_event = size_t(npts) * 2 * Proc::K * Proc::NHEL * sizeof(T);
+    int64_t b = int64_t(kJBufBytes / per_event);
+    b = b > kPartBatch ? kPartBatch : (b < 64 ? 64 : b);
+    return n < b ? n : b;
+}
+
+// Double-precision pipeline over `slots` slots: per-slot data, then batches
+// through the (chunk, range) kernels and the colour sum.  list == NULL: slot
+// i is event i; otherwise slot i is event list[i] for i < count[0].
+template <class Proc>
+hipError_t launch_split64(const split_launchers<Proc>& L, const double* mom, int64_t n, const int64_t* list,
+                          const unsigned long long* count, int64_t slots, const double* w_in, const qcd_launch& a,
+                          double* out, double* me0, hipStream_t s, bool timed) {
+    using ED = event_data<Proc, double>;
+    const int64_t B = part_batch<Proc, double>(slots, a.npts);
+    ED* ev = nullptr;
+    double* jbuf = nullptr;
+    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(ED) * size_t(slots), s);
+    if (err != hipSuccess) return err;
+    err = hipMallocAsync(reinterpret_cast<void**>(&jbuf),
+                         sizeof(double) * size_t(B) * a.npts * 2 * Proc::K * Proc::NHEL, s);
+    if (err != hipSuccess) {
+        (void)hipFreeAsync(ev, s);
+        return err;
+    }
+    hipLaunchKernelGGL((qcd_setup64_kernel<Proc>), dim3(unsigned((slots + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       mom, n, a.mt, list, count, slots, ev);
+    err = hipGetLastError();
+    if (timed) mark(a.t0, s);
+    for (int64_t e0 = 0; e0 < slots && err == hipSuccess; e0 += B) {
+        const int64_t nb = slots - e0 < B ? slots - e0 : B;
+        for (int q = 0; q < Proc::NCHUNK64 * Proc::NFR && err == hipSuccess; ++q)
+            err = L.fr[q](ev, count, e0, nb, jbuf, a, s);
+        if (err == hipSuccess) {
+            hipLaunchKernelGGL((qcd_colour64_kernel<Proc>), dim3(unsigned((nb + kBlock / 64 - 1) / (kBlock / 64))),
+                               dim3(kBlock), 0, s, jbuf, list, count, e0, nb, w_in, n, a, out, me0);
+            err = hipGetLastError();
+        }
+    }
+    if (timed) mark(a.t1, s);
+    hipError_t f1 = hipFreeAsync(jbuf, s), f2 = hipFreeAsync(ev, s);
+    return err != hipSuccess ? err : (f1 != hipSuccess ? f1 : f2);
+}
+
+// A split program: FP64 runs the double-precision pipeline over all events;
+// mixed precision runs the per-event data (listing ill-conditioned events
+// when the re-evaluation is on), batches through the single-precision parts
+// (and the matrix-core colour sum when selected), then the listed events
+// through the double-precision pipeline.
+template <class Proc>
+hipError_t launch_split(const split_launchers<Proc>& L, int fp64, const double* mom, const double* w_in, int64_t n,
+                        const qcd_launch& a, double* out, double* me0, hipStream_t s) {
+    if (fp64) return launch_split64<Proc>(L, mom, n, nullptr, nullptr, n, w_in, a, out, me0, s, true);
+    using ED = event_data<Proc, float>;
+    const bool rescue = a.rescue_tau > 0.0;
+    const int64_t B = part_batch<Proc, float>(n, a.npts);
+    ED* ev = nullptr;
+    float* jbuf = nullptr;
+    int64_t* buf = nullptr;
+    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(ED) * size_t(n), s);
+    if (err != hipSuccess) return err;
+    err = hipMallocAsync(reinterpret_cast<void**>(&jbuf), sizeof(float) * size_t(B) * a.npts * 2 * Proc::K * Proc::NHEL,
+                         s);
+    if (err == hipSuccess && rescue)
+        err = hipMallocAsync(reinterpret_cast<void**>(&buf), sizeof(int64_t) * size_t(n + 1), s);
+    if (err != hipSuccess) {
+        if (jbuf) (void)hipFreeAsync(jbuf, s);
+        (void)hipFreeAsync(ev, s);
+        return err;
+    }
+    unsigned long long* count = rescue ? reinterpret_cast<unsigned long long*>(buf) : nullptr;
+    int64_t* list = rescue ? buf + 1 : nullptr;
+    if (rescue) hipLaunchKernelGGL((rescue_reset_kernel<Proc>), dim3(1), dim3(64), 0, s, count);
+    hipLaunchKernelGGL((qcd_setup_kernel<Proc, float>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       mom, n, a.mt, ev, rescue ? a.rescue_tau : 0.0, count, list);
+    err = hipGetLastError();
+    mark(a.t0, s);
+    for (int64_t e0 = 0; e0 < n && err == hipSuccess; e0 += B) {
+        const int64_t nb = n - e0 < B ? n - e0 : B;
+        for (int c = 0; c < Proc::NCHUNK && err == hipSuccess; ++c)
+            err = L.part[c](ev, e0, nb, jbuf, w_in, n, a, out, me0, s);
+        if (err == hipSuccess) err = launch_colour_mfma<Proc>(jbuf, e0, nb, w_in, n, a, out, me0, s);
+    }
+    mark(a.t1, s);
+    hipError_t f1 = hipFreeAsync(jbuf, s), f2 = hipFreeAsync(ev, s);
+    if (err == hipSuccess && rescue)
+        err = launch_split64<Proc>(L, mom, n, list, count, n, w_in, a, out, me0, s, false);
+    hipError_t f3 = rescue ? hipFreeAsync(buf, s) : hipSuccess;
+    return err != hipSuccess ? err : (f1 != hipSuccess ? f1 : (f2 != hipSuccess ? f2 : f3));
+}
 
 // Launch the reweight (mode 0) or single-point (mode 1) kernels of Proc at the
 // requested arithmetic; returns the launch status.

@@ -161,9 +161,13 @@ gemm_bf16(const uint16_t* __restrict__ A, int64_t sam, int64_t sak, const uint16
 // kd[r] = kappa_k - 1.  Features: the 24 momentum components over sqrt(s)/2,
 // (kappa - 1)/0.2, then for the 14 particle pairs (i < j) other than the two
 // beams v_ij = 2 p_i.p_j / s and log(v_ij); absent particles give zeros.
+// The points' kappa values travel by value with each launch.
+struct kappa_set {
+    double k[MGRW_MAX_POINTS];
+};
+
 __global__ void features_kernel(const double* __restrict__ mom, int n_ext, int64_t n, int64_t e0, int P,
-                                const double* __restrict__ kappa, int64_t rows, uint16_t* __restrict__ x,
-                                float* __restrict__ kd) {
+                                kappa_set kappa, int64_t rows, uint16_t* __restrict__ x, float* __restrict__ kd) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= rows) return;
     const int64_t e = e0 + r / P;
@@ -172,7 +176,7 @@ __global__ void features_kernel(const double* __restrict__ mom, int n_ext, int64
     const double inv = 2.0 / rs;
     uint16_t* xr = x + r * K0;
     for (int i = 0; i < 24; ++i) xr[i] = i < n_ext * 4 ? f2bf(float(mom[int64_t(i) * n + e] * inv)) : uint16_t(0);
-    xr[24] = f2bf(float((kappa[k] - 1.0) / 0.2));
+    xr[24] = f2bf(float((kappa.k[k] - 1.0) / 0.2));
     int c = NRAW;
     for (int i = 0; i < 6; ++i)
         for (int j = i + 1; j < 6; ++j) {
@@ -191,7 +195,7 @@ __global__ void features_kernel(const double* __restrict__ mom, int n_ext, int64
             ++c;
         }
     for (int i = NFEAT; i < K0; ++i) xr[i] = 0;
-    kd[r] = float(kappa[k] - 1.0);
+    kd[r] = float(kappa.k[k] - 1.0);
 }
 
 // Gather training samples s = perm[b0 + r]: event s / P, point s % P, from
@@ -374,33 +378,40 @@ __global__ void sum_rows(const double* __restrict__ w, int P, int64_t n, double*
     if (threadIdx.x == 0) part[int64_t(k) * gridDim.x + blockIdx.x] = red[0];
 }
 
-// Audit: per point, sums over audited events of (exact - surrogate), of the
-// relative error and its square; then the exact weights replace the surrogate
+// Audit: per point, sums over audited events of (exact - surrogate), and of
+// the relative error |su/ex - 1| and its square with the number of events
+// entering them (those with a finite non-zero exact weight and a finite
+// ratio: a zero input weight makes both weights zero, |M|^2 = 0 at the base
+// makes the exact one NaN); then the exact weights replace the surrogate
 // ones.  One block per point (audits are small).
 __global__ void audit_kernel(const int64_t* __restrict__ idx, int64_t na, const double* __restrict__ w_exact,
                              int64_t n, double* __restrict__ w_out, double* __restrict__ stats) {
-    __shared__ double red[3][256];
+    __shared__ double red[4][256];
     const int k = blockIdx.x;
-    double d = 0.0, e1 = 0.0, e2 = 0.0;
+    double d = 0.0, e1 = 0.0, e2 = 0.0, m = 0.0;
     for (int64_t a = threadIdx.x; a < na; a += 256) {
         const double ex = w_exact[int64_t(k) * na + a];
         const double su = w_out[int64_t(k) * n + idx[a]];
         d += ex - su;
         const double r = fabs(su / ex - 1.0);
-        e1 += r;
-        e2 += r * r;
+        if (ex != 0.0 && isfinite(r)) {
+            e1 += r;
+            e2 += r * r;
+            m += 1.0;
+        }
     }
     red[0][threadIdx.x] = d;
     red[1][threadIdx.x] = e1;
     red[2][threadIdx.x] = e2;
+    red[3][threadIdx.x] = m;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o)
-            for (int j = 0; j < 3; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
+            for (int j = 0; j < 4; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int j = 0; j < 3; ++j) stats[k * 3 + j] = red[j][0];
+        for (int j = 0; j < 4; ++j) stats[k * 4 + j] = red[j][0];
     __syncthreads();
     for (int64_t a = threadIdx.x; a < na; a += 256) w_out[int64_t(k) * n + idx[a]] = w_exact[int64_t(k) * na + a];
 }
@@ -424,7 +435,7 @@ constexpr int FR = 128;         // rows per workgroup
 constexpr int LDA = H + 8;      // LDS row stride (bfloat16)
 
 __global__ void __launch_bounds__(256, 2)
-mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restrict__ kappa, int rows, int64_t e0,
+mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, kappa_set kappa, int rows, int64_t e0,
                  int64_t n_events, const uint16_t* __restrict__ wbf, const float* __restrict__ par,
                  const double* __restrict__ w_in, double* __restrict__ w_out) {
     __shared__ __align__(16) uint16_t act[FR][LDA];
@@ -438,7 +449,7 @@ mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restri
         uint4* dst = reinterpret_cast<uint4*>(&act[mrow][q * 32]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) dst[i] = live ? src[i] : make_uint4(0u, 0u, 0u, 0u);
-        if (q == 0 && r < rows) act[mrow][NRAW - 1] = f2bf(float((kappa[r % P] - 1.0) / 0.2));
+        if (q == 0 && r < rows) act[mrow][NRAW - 1] = f2bf(float((kappa.k[r % P] - 1.0) / 0.2));
     }
     __syncthreads();
 #pragma unroll 1
@@ -501,7 +512,7 @@ mlp_infer_kernel(const uint16_t* __restrict__ xev, int P, const double* __restri
     if (q == 0 && r < rows) {
         const int k = r % P;
         const int64_t e = e0 + r / P;
-        const float yh = float(kappa[k] - 1.0) * (h + par[OFF_B5]);
+        const float yh = float(kappa.k[k] - 1.0) * (h + par[OFF_B5]);
         const double w = w_in ? w_in[e] : 1.0;
         w_out[int64_t(k) * n_events + e] = w * exp(double(yh));
     }
@@ -548,7 +559,8 @@ audit_scan_kernel(const unsigned* __restrict__ counts, int64_t nb, int64_t* __re
 }
 
 __global__ void __launch_bounds__(256)
-audit_fill_kernel(uint64_t seed, double f, int64_t n, const int64_t* __restrict__ offsets, int64_t* __restrict__ idx) {
+audit_fill_kernel(uint64_t seed, double f, int64_t n, const int64_t* __restrict__ offsets, int64_t na,
+                  int64_t* __restrict__ idx) {
     const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
     const bool sel = e < n && u01(seed, 2, uint64_t(e)) < f;
     __shared__ unsigned flags[256];
@@ -557,7 +569,8 @@ audit_fill_kernel(uint64_t seed, double f, int64_t n, const int64_t* __restrict_
     if (sel) {
         unsigned pos = 0;
         for (unsigned i = 0; i < threadIdx.x; ++i) pos += flags[i];
-        idx[offsets[blockIdx.x] + pos] = e;
+        const int64_t at = offsets[blockIdx.x] + pos;
+        if (at < na) idx[at] = e;   // na: the same count, made on the host
     }
 }
 
@@ -578,6 +591,21 @@ struct dbuf {   // device buffer owned by the library
     }
     ~dbuf() {
         if (p) (void)hipFree(p);
+    }
+};
+
+template <typename T>
+struct sbuf {   // scratch of one call, allocated and freed in the order of its stream
+    T* p = nullptr;
+    hipStream_t s;
+    explicit sbuf(hipStream_t st) : s(st) {}
+    sbuf(const sbuf&) = delete;
+    sbuf& operator=(const sbuf&) = delete;
+    hipError_t alloc(size_t count) {
+        return hipMallocAsync(reinterpret_cast<void**>(&p), std::max<size_t>(count, 1) * sizeof(T), s);
+    }
+    ~sbuf() {
+        if (p) (void)hipFreeAsync(p, s);
     }
 };
 
@@ -740,6 +768,10 @@ void adam(surrogate* s, float lr, hipStream_t st) {
 mgrw_status check_qcd_kappa_only(const mgrw_process* p) {
     if (p->proc == MGRW_EE_MUMU || p->proc == MGRW_EE_5A)
         return set_error(MGRW_ERR_UNSUPPORTED, "surrogate: QCD processes only");
+    // the network's output (kappa - 1) h and its kappa feature vanish at
+    // kappa = 1, where the target log(|M_k|^2 / |M_base|^2) must vanish too
+    if (p->base.kappa_ttg != 1.0)
+        return set_error(MGRW_ERR_UNSUPPORTED, "surrogate: the base point must have kappa_ttg = 1");
     if (p->n_points == 0) return set_error(MGRW_ERR_STATE, "no parameter points set");
     for (int k = 0; k < p->n_points; ++k) {
         const mgrw_params& q = p->points[k];
@@ -749,13 +781,19 @@ mgrw_status check_qcd_kappa_only(const mgrw_process* p) {
     return MGRW_OK;
 }
 
-mgrw_status upload_kappas(const mgrw_process* p, dbuf<double>& kap, hipStream_t st) {
-    std::vector<double> k(p->n_points);
-    for (int i = 0; i < p->n_points; ++i) k[i] = p->points[i].kappa_ttg;
-    HIPCHK(kap.alloc(k.size()));
-    HIPCHK(hipMemcpyAsync(kap.p, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
-    return MGRW_OK;
+kappa_set kappas_of(const mgrw_process* p) {
+    kappa_set k{};
+    for (int i = 0; i < p->n_points; ++i) k.k[i] = p->points[i].kappa_ttg;
+    return k;
+}
+
+// Number of events with u(seed, 2, e) < f: the audit set's size, the same
+// draw the device makes (computed here so that the call need not wait for
+// the device before sizing the audit).
+int64_t audit_size(uint64_t seed, double f, int64_t n) {
+    int64_t c = 0;
+    for (int64_t e = 0; e < n; ++e) c += u01(seed, 2, uint64_t(e)) < f;
+    return c;
 }
 
 // Fit a freshly initialised network (seeded) to ns samples: bfloat16
@@ -877,6 +915,9 @@ mgrw_status mgrw_surrogate_fwd_bwd(mgrw_process* p, const float* x, const float*
     if (!p || !x || !kd || !y || !pred || !grad || !loss) return set_error(MGRW_ERR_ARG, "null argument");
     if (m <= 0 || m % 64 != 0 || m > (int64_t(1) << 24)) return set_error(MGRW_ERR_ARG, "m must be a positive multiple of 64");
     if (!p->sur || !p->sur->par.p) return set_error(MGRW_ERR_STATE, "no surrogate");
+    if (check_device_ptr(x, "x", false) != MGRW_OK || check_device_ptr(kd, "kd", false) != MGRW_OK ||
+        check_device_ptr(y, "y", false) != MGRW_OK || check_device_ptr(pred, "pred", false) != MGRW_OK)
+        return MGRW_ERR_ARG;
     surrogate* s = p->sur;
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIPCHK(ensure_rows(s, m));
@@ -912,8 +953,10 @@ mgrw_status mgrw_surrogate_train(mgrw_process* p, const double* mom, int64_t n_e
     int n_ext = 0;
     mgrw_process_info(p, &n_ext, nullptr, nullptr, nullptr);
 
+    if (check_device_ptr(mom, "mom", false) != MGRW_OK) return MGRW_ERR_ARG;
+
     // labels from the exact kernels
-    dbuf<double> wex, kap;
+    dbuf<double> wex;
     HIPCHK(wex.alloc(size_t(ns)));
     mgrw_status r = mgrw_reweight(p, mom, nullptr, n_events, wex.p, nullptr, stream);
     if (r != MGRW_OK) return r;
@@ -923,10 +966,8 @@ mgrw_status mgrw_surrogate_train(mgrw_process* p, const double* mom, int64_t n_e
     HIPCHK(kdall.alloc(size_t(ns)));
     HIPCHK(xall.alloc(size_t(ns) * K0));
     hipLaunchKernelGGL(labels_kernel, dim3(unsigned((ns + 255) / 256)), dim3(256), 0, st, wex.p, P, n_events, yall.p);
-    r = upload_kappas(p, kap, st);
-    if (r != MGRW_OK) return r;
     hipLaunchKernelGGL(features_kernel, dim3(unsigned((ns + 255) / 256)), dim3(256), 0, st, mom, n_ext, n_events,
-                       int64_t(0), P, kap.p, ns, xall.p, kdall.p);
+                       int64_t(0), P, kappas_of(p), ns, xall.p, kdall.p);
     HIPCHK(hipGetLastError());
 
     return train_core(p, xall.p, kdall.p, yall.p, ns, cfg, loss_out, st);
@@ -939,6 +980,9 @@ mgrw_status mgrw_surrogate_train_samples(mgrw_process* p, const float* x, const 
     if (cfg->epochs < 1 || cfg->batch < 64 || cfg->batch % 64 != 0 || !(cfg->lr > 0))
         return set_error(MGRW_ERR_ARG, "bad training configuration");
     if (m < cfg->batch) return set_error(MGRW_ERR_ARG, "fewer samples than one batch");
+    if (check_device_ptr(x, "x", false) != MGRW_OK || check_device_ptr(kd, "kd", false) != MGRW_OK ||
+        check_device_ptr(y, "y", false) != MGRW_OK)
+        return MGRW_ERR_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
     dbuf<uint16_t> xall;
     dbuf<float> kdall, yall;
@@ -963,89 +1007,88 @@ mgrw_status mgrw_reweight_surrogate(mgrw_process* p, const double* mom, const do
     if (n_events < 0) return set_error(MGRW_ERR_ARG, "n_events < 0");
     if (fell_back) *fell_back = 0;
     if (n_events == 0) return MGRW_OK;
-    if (!mom || !w_out) return set_error(MGRW_ERR_ARG, "null mom or w_out");
+    if ((r = check_device_ptr(mom, "mom", false)) != MGRW_OK) return r;
+    if ((r = check_device_ptr(w_out, "w_out", false)) != MGRW_OK) return r;
+    if ((r = check_device_ptr(w_in, "w_in", true)) != MGRW_OK) return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
     surrogate* s = p->sur;
     const int P = p->n_points;
+    const kappa_set kap = kappas_of(p);
     int n_ext = 0;
     mgrw_process_info(p, &n_ext, nullptr, nullptr, nullptr);
-    dbuf<double> kap;
-    r = upload_kappas(p, kap, st);
-    if (r != MGRW_OK) return r;
+    // Every buffer below is allocated and freed in stream order; the only
+    // wait is for the audit statistics at the end.
 
     // 1. surrogate weights for every (event, point), in chunks of events: the
     // event features once per event, then the fused network over its P rows
     // (only the per-event features need a buffer: the activations stay in LDS)
     const int64_t chunk_ev = std::min<int64_t>(n_events, std::max<int64_t>(1, (int64_t(1) << 20) / P));
-    dbuf<uint16_t> xev;
-    dbuf<float> kdev;
+    sbuf<uint16_t> xev(st);
+    sbuf<float> kdev(st);
     HIPCHK(xev.alloc(size_t(chunk_ev) * K0));
     HIPCHK(kdev.alloc(size_t(chunk_ev)));
     for (int64_t e0 = 0; e0 < n_events; e0 += chunk_ev) {
         const int64_t ne = std::min(chunk_ev, n_events - e0);
         const int64_t rows = ne * P;
         hipLaunchKernelGGL(features_kernel, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, mom, n_ext,
-                           n_events, e0, 1, kap.p, ne, xev.p, kdev.p);
+                           n_events, e0, 1, kap, ne, xev.p, kdev.p);
         hipLaunchKernelGGL(mlp_infer_kernel, dim3(unsigned((rows + FR - 1) / FR)), dim3(256), 0, st, xev.p, P,
-                           kap.p, int(rows), e0, n_events, s->pbf.p, s->par.p, w_in, w_out);
+                           kap, int(rows), e0, n_events, s->pbf.p, s->par.p, w_in, w_out);
     }
     HIPCHK(hipGetLastError());
 
-    // 2. surrogate sums per point
+    // 2. surrogate sums per point; partial sums, then the audit statistics
     const unsigned sblocks = 256;
-    dbuf<double> part;
-    HIPCHK(part.alloc(size_t(P) * sblocks + size_t(P) * 3));
+    sbuf<double> part(st);
+    HIPCHK(part.alloc(size_t(P) * sblocks + size_t(P) * 4));
+    double* astats = part.p + size_t(P) * sblocks;
     hipLaunchKernelGGL(sum_rows, dim3(sblocks, unsigned(P)), dim3(256), 0, st, w_out, P, n_events, part.p);
 
-    // 3. audit: events with u(seed, e) < fraction, evaluated exactly (selected
-    // and compacted on the device; the count is read back)
-    const int64_t nblk = (n_events + 255) / 256;
-    dbuf<unsigned> acount;
-    dbuf<int64_t> aoff;
-    HIPCHK(acount.alloc(size_t(nblk)));
-    HIPCHK(aoff.alloc(size_t(nblk) + 1));
-    hipLaunchKernelGGL(audit_count_kernel, dim3(unsigned(nblk)), dim3(256), 0, st, uint64_t(seed), audit_fraction,
-                       n_events, acount.p);
-    hipLaunchKernelGGL(audit_scan_kernel, dim3(1), dim3(256), 0, st, acount.p, nblk, aoff.p);
-    int64_t na = 0;
-    HIPCHK(hipMemcpyAsync(&na, aoff.p + nblk, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    std::vector<double> stats(size_t(P) * 3, 0.0);
+    // 3. audit: events with u(seed, e) < fraction, selected and compacted in
+    // event order on the device, evaluated exactly
+    const int64_t na = audit_size(seed, audit_fraction, n_events);
     if (na > 0) {
-        dbuf<int64_t> didx;
-        dbuf<double> mom_a, w_a, w_ex;
+        const int64_t nblk = (n_events + 255) / 256;
+        sbuf<unsigned> acount(st);
+        sbuf<int64_t> aoff(st), didx(st);
+        sbuf<double> mom_a(st), w_a(st), w_ex(st);
+        HIPCHK(acount.alloc(size_t(nblk)));
+        HIPCHK(aoff.alloc(size_t(nblk) + 1));
         HIPCHK(didx.alloc(size_t(na)));
         HIPCHK(mom_a.alloc(size_t(na) * n_ext * 4));
         HIPCHK(w_a.alloc(size_t(na)));
         HIPCHK(w_ex.alloc(size_t(na) * P));
+        hipLaunchKernelGGL(audit_count_kernel, dim3(unsigned(nblk)), dim3(256), 0, st, uint64_t(seed), audit_fraction,
+                           n_events, acount.p);
+        hipLaunchKernelGGL(audit_scan_kernel, dim3(1), dim3(256), 0, st, acount.p, nblk, aoff.p);
         hipLaunchKernelGGL(audit_fill_kernel, dim3(unsigned(nblk)), dim3(256), 0, st, uint64_t(seed), audit_fraction,
-                           n_events, aoff.p, didx.p);
+                           n_events, aoff.p, na, didx.p);
         hipLaunchKernelGGL(gather_events, dim3(unsigned((na + 255) / 256)), dim3(256), 0, st, mom, n_ext, n_events,
                            didx.p, na, w_in, mom_a.p, w_a.p);
         r = mgrw_reweight(p, mom_a.p, w_a.p, na, w_ex.p, nullptr, stream);
         if (r != MGRW_OK) return r;
         hipLaunchKernelGGL(audit_kernel, dim3(unsigned(P)), dim3(256), 0, st, didx.p, na, w_ex.p, n_events, w_out,
-                           part.p + size_t(P) * sblocks);
+                           astats);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(stats.data(), part.p + size_t(P) * sblocks, size_t(P) * 3 * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
     }
-    std::vector<double> sums(size_t(P) * sblocks);
-    HIPCHK(hipMemcpyAsync(sums.data(), part.p, sums.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> host(size_t(P) * sblocks + size_t(P) * 4, 0.0);
+    HIPCHK(hipMemcpyAsync(host.data(), part.p, (na > 0 ? host.size() : size_t(P) * sblocks) * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    const double* stats = host.data() + size_t(P) * sblocks;
     bool bad = false;
     for (int k = 0; k < P; ++k) {
         double ssur = 0.0;
-        for (unsigned b = 0; b < sblocks; ++b) ssur += sums[size_t(k) * sblocks + b];
-        const double d = stats[k * 3], e1 = stats[k * 3 + 1], e2 = stats[k * 3 + 2];
-        const double mean = na > 0 ? e1 / double(na) : 0.0;
-        const double var = na > 1 ? std::max(0.0, (e2 - double(na) * mean * mean) / double(na - 1)) : 0.0;
-        if (na > 0 && mean > max_audit_error) bad = true;
+        for (unsigned b = 0; b < sblocks; ++b) ssur += host[size_t(k) * sblocks + b];
+        const double d = stats[k * 4], e1 = stats[k * 4 + 1], e2 = stats[k * 4 + 2], m = stats[k * 4 + 3];
+        const double mean = m > 0 ? e1 / m : 0.0;
+        const double var = m > 1 ? std::max(0.0, (e2 - m * mean * mean) / (m - 1)) : 0.0;
+        if (m > 0 && !(mean <= max_audit_error)) bad = true;
         if (audit_stats) {
             audit_stats[k * 5 + 0] = ssur + d / audit_fraction;
             audit_stats[k * 5 + 1] = ssur;
             audit_stats[k * 5 + 2] = mean;
-            audit_stats[k * 5 + 3] = na > 0 ? std::sqrt(var / double(na)) : 0.0;
+            audit_stats[k * 5 + 3] = m > 0 ? std::sqrt(var / m) : 0.0;
             audit_stats[k * 5 + 4] = double(na);
         }
     }

@@ -285,9 +285,12 @@ class Emitter:
     external wavefunctions, the t tbar current and the single-gluon row and
     column currents are shared by all groups."""
 
-    def __init__(self, ng, global_leaf_lr=True, kpoly=False):
+    def __init__(self, ng, global_leaf_lr=True, kpoly=False, flow_range=None):
         self.ng = ng
         self.kpoly = kpoly          # accumulate J per power of kappa (J[(k-1)*K + w])
+        # (lo, hi): accumulate only the flows lo <= w < hi, into J[w - lo]; diagrams
+        # with no term there are left out, and so are the currents only they use
+        self.flow_range = flow_range
         self.full = (1 << ng) - 1
         self.lines = []
         self.nvar = 0
@@ -402,11 +405,21 @@ class Emitter:
         return "jtt"
 
     # ---- amplitudes
+    def wanted(self, seq):
+        if self.flow_range is None:
+            return True
+        lo, hi = self.flow_range
+        return any(lo <= self.flow_index[w] < hi for w in diagram_colour(seq))
+
     def accumulate(self, amp, seq):
         col = diagram_colour(seq)
         for w, c in sorted(col.items(), key=lambda x: self.flow_index[x[0]]):
             assert c in (1, -1), (seq, w, c)
             j = self.flow_index[w]
+            if self.flow_range is not None:
+                if not self.flow_range[0] <= j < self.flow_range[1]:
+                    continue
+                j -= self.flow_range[0]
             if self.kpoly:   # one top-gluon vertex per attached tree: kappa^len(seq)
                 j += (len(seq) - 1) * len(self.flows)
             op = "+" if c > 0 else "-"
@@ -414,6 +427,8 @@ class Emitter:
             self.n_jterms += 1
 
     def close_ttg(self, seq, j):
+        if not self.wanted(seq):
+            return
         left, right = self.L(seq[:j]), self.R(seq[j + 1:])
         cur = self.tree(seq[j])
         a = self.var("a")
@@ -423,6 +438,8 @@ class Emitter:
         self.accumulate(a, seq)
 
     def close_root(self, seq):
+        if not self.wanted(seq):
+            return
         t = seq[0]
         jtt = self.tt_current()
         kids = [self.tree(k) for k in t.kids]
@@ -548,12 +565,20 @@ def bf16_split_table(num, kp):
     return hi, lo
 
 
-def emit_process(name, ng, chunks=1):
+def emit_process(name, ng, chunks=1, fp64_split=None):
     """C++ source of the process struct for g g -> t tbar + (ng-2) g.
 
     With chunks > 1 the per-helicity program is split into that many
     functions amplitude_part<C> over consecutive closing groups, each adding
-    its diagrams to J; amplitude() zeroes J and runs all parts."""
+    its diagrams to J; amplitude() zeroes J and runs all parts.
+
+    fp64_split = (nch, nfr) also emits the program cut into nch chunks of
+    closing groups times nfr equal ranges of colour flows,
+    amplitude_fr<C, R>: chunk C's diagrams that have a term in flow range R,
+    accumulated into that range only (J[w - R K/nfr]).  A diagram with terms in
+    several ranges, and the currents it needs, appear in each of them; in
+    exchange only K/nfr flow amplitudes are live at a time, which is what
+    lets the program run in double precision."""
     from math import factorial, gcd
     em = Emitter(ng)
     if chunks > 1:
@@ -575,6 +600,21 @@ def emit_process(name, ng, chunks=1):
         body = None
     else:
         body = em.program()
+    fr_ems = {}
+    if fp64_split is not None:
+        nch64, nfr = fp64_split
+        kf = len(em.flows)
+        assert kf % nfr == 0
+        kr = kf // nfr
+        parts64 = split_groups(ng, nch64)
+        for c, p in enumerate(parts64):
+            for r in range(nfr):
+                e = Emitter(ng, flow_range=(r * kr, (r + 1) * kr))
+                e.program(set(p))
+                fr_ems[(c, r)] = (e, p)
+                # every kinematic quantity the split program needs is in kin<T>
+                assert e.P_needed <= em.P_needed and e.iP_needed <= em.iP_needed
+                assert e.qL_needed <= em.qL_needed and e.qR_needed <= em.qR_needed
     K = len(em.flows)
     next_ = ng + 2
     cf = colour_matrix_loops(ng)
@@ -703,6 +743,29 @@ def emit_process(name, ng, chunks=1):
         for ci in range(len(part_ems)):
             w(f"    amplitude_part{ci}<T>(w, k, c, J);")
         w("  }")
+    if fr_ems:
+        nch64, nfr = fp64_split
+        w(f"  // Double-precision instance: {nch64} chunks of closing groups x {nfr} ranges of")
+        w(f"  // {K // nfr} colour flows; amplitude_fr<C, R> adds chunk C's terms in flow range R")
+        w("  // to J[0 .. KR-1] (flow R*KR + i in J[i]).")
+        w(f"  static constexpr int NCHUNK64 = {nch64};")
+        w(f"  static constexpr int NFR = {nfr};")
+        w(f"  static constexpr int KR = {K // nfr};")
+        for (c, r), (e, p) in sorted(fr_ems.items()):
+            w(f"  // chunk {c} (closing groups " + ", ".join(
+                "leaf" if g == "leaf" else str(bits(g)) for g in p) + f"), flows {r * (K // nfr)}..{(r + 1) * (K // nfr) - 1}")
+            w("  template <typename T, typename KN>")
+            w(f"  static MGRW_HD void amplitude_fr{c}_{r}(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {{")
+            for line in e.lines:
+                w("    " + line)
+            w("  }")
+        w("  template <int C, int R, typename T, typename KN>")
+        w("  static MGRW_HD void amplitude_fr(const ext<T>& w, const KN& k, const coup<T>& c, cx<T>* J) {")
+        first = True
+        for (c, r) in sorted(fr_ems):
+            w(f"    {'if' if first else 'else if'} constexpr (C == {c} && R == {r}) amplitude_fr{c}_{r}<T>(w, k, c, J);")
+            first = False
+        w("  }")
     if body is not None:
         # kappa-polynomial form of the same diagrams: J split by power of kappa
         ek = Emitter(ng, kpoly=True)
@@ -758,6 +821,13 @@ def emit_process(name, ng, chunks=1):
     for row in num:
         w("    {" + ", ".join(str(x) for x in row) + "},")
     w("  };")
+    if fr_ems:
+        # the numerators as doubles, for the double-precision colour sum that
+        # streams J from memory (row-major; CF is symmetric)
+        w("  static constexpr double CF_DBL[K * K] = {")
+        for row in num:
+            w("    " + ", ".join(f"{x}.0" for x in row) + ",")
+        w("  };")
     if chunks > 1:
         # colour matrix for the matrix cores: numerators padded to a multiple of
         # 32 and split exactly into two bfloat16 terms (bit patterns)

@@ -96,7 +96,15 @@ def test_colour_mfma_option_only_for_the_split_process(L):
 def test_unsupported_precisions_and_processes(L):
     h = ctypes.c_void_p()
     base = bd.make_params()
-    assert L.mgrw_create_process(bd.GG_TTGGG, bd.FP64, ctypes.byref(base), ctypes.byref(h)) == bd.ERR_UNSUPPORTED
+    assert L.mgrw_create_process(bd.EE_MUMU, bd.MIXED, ctypes.byref(base), ctypes.byref(h)) == bd.ERR_UNSUPPORTED
+    # g g -> t tbar g g g runs in both precisions; its FP64 re-evaluation is a
+    # mixed-precision option
+    assert L.mgrw_create_process(bd.GG_TTGGG, bd.FP64, ctypes.byref(base), ctypes.byref(h)) == bd.OK
+    assert L.mgrw_set_option(h, 2, 3000) == bd.ERR_UNSUPPORTED
+    L.mgrw_destroy_process(h)
+    assert L.mgrw_create_process(bd.GG_TTGGG, bd.MIXED, ctypes.byref(base), ctypes.byref(h)) == bd.OK
+    assert L.mgrw_set_option(h, 2, 3000) == bd.OK
+    L.mgrw_destroy_process(h)
     assert L.mgrw_create_process(bd.EE_5A + 1, bd.FP64, ctypes.byref(base), ctypes.byref(h)) == bd.ERR_ARG
     assert L.mgrw_create_process(bd.EE_5A, bd.FP64, ctypes.byref(base), ctypes.byref(h)) == bd.OK
     L.mgrw_destroy_process(h)
@@ -136,4 +144,17 @@ def test_host_reweight_argument_errors(L):
     assert L.mgrw_reweight_host(p._h, None, None, 10, None, None, 0) == bd.ERR_ARG     # null arrays
     assert L.mgrw_reweight_host(p._h, None, None, 0, None, None, 0) == bd.OK           # nothing to do
     assert L.mgrw_reweight_host(None, None, None, 0, None, None, 0) == bd.ERR_ARG
+    p.close()
+
+
+def test_surrogate_needs_unit_base_kappa(L):
+    """The network's prediction vanishes at kappa = 1 by construction, so a
+    base point with another kappa is refused before the device is touched."""
+    p = bd.Process("gg_ttgg", "mixed", {"kappa_ttg": 1.2})
+    p.set_params([{"kappa_ttg": 0.9}, {"kappa_ttg": 1.1}])
+    cfg = bd.TrainConfig(2, 1024, 1e-3, 0.7, 1)
+    assert L.mgrw_surrogate_train(p._h, None, 10, ctypes.byref(cfg), None, None) == bd.ERR_UNSUPPORTED
+    assert b"kappa_ttg = 1" in L.mgrw_last_error()
+    st = (ctypes.c_double * 10)()
+    assert L.mgrw_reweight_surrogate(p._h, None, None, 10, 0.01, 1, 0.01, None, st, None, None) == bd.ERR_UNSUPPORTED
     p.close()

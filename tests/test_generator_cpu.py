@@ -167,3 +167,26 @@ def test_colour_matrix_bf16_split_is_exact():
             assert P.bf16_value(hi[r * 128 + c]) + P.bf16_value(lo[r * 128 + c]) == v
     assert max(abs(x) for row in num for x in row) < 1 << 16
     assert Fraction(num[0][0], den) == cf[0][0]
+
+
+def test_host_gg_ttggg_whole_and_split_programs_match_oracle():
+    """g g -> t tbar g g g: the whole generated program and its double-
+    precision cut into (closing-group chunk x colour-flow range) functions,
+    where a diagram with terms in several ranges is evaluated once per range
+    and adds only that range's terms, against the oracle's recursion at
+    kappa = 1 and kappa != 1."""
+    lib = hostlib()
+    n = 2
+    mom = np.ascontiguousarray(generate_events("gg_ttggg", n, first_event=77))
+    kap = [1.0, 0.83, 1.17]
+    gs = np.sqrt(4 * np.pi * ALS)
+    pts = np.array([[gs, k] for k in kap]).ravel()
+    whole = np.zeros((len(kap), n))
+    split = np.zeros((len(kap), n))
+    assert lib.mgrw_host_qcd_me(5, _dp(mom), ctypes.c_int64(n), ctypes.c_double(MT), _dp(pts), len(kap),
+                                _dp(whole)) == 0
+    assert lib.mgrw_host_qcd_me_split(5, _dp(mom), ctypes.c_int64(n), ctypes.c_double(MT), _dp(pts), len(kap),
+                                      _dp(split)) == 0
+    ref = oracle.qcd_me(5, mom, [(ALS, MT, k) for k in kap])
+    assert np.max(np.abs(whole / ref - 1)) < 1e-12
+    assert np.max(np.abs(split / ref - 1)) < 1e-12
