@@ -51,10 +51,7 @@ def kernel_fingerprint(proc="gg_ttgg"):
 # flops of the events it evaluates, from SQ_INSTS_VALU_{FMA,MUL,ADD}_F32
 # (profiles/), for the same kernel sources as MEASURED_TRAFFIC.
 MEASURED_EXEC_RATIO = {("gg_ttgg", "mixed", "fc76df9a4ca7ced9"): 0.885}
-RESCUE_TAU = 3e-3   # the library's default FP64 re-evaluation threshold (mixed precision)
-
-
-def rescued_events(mom_np, tau=RESCUE_TAU):
+def rescued_events(mom_np, tau):
     """Events the mixed-precision call leaves to its FP64 re-evaluation: a
     gluon pair other than the two beams with |2 p_i.p_j| / s below tau (the
     library's criterion, evaluated here in float64)."""
@@ -363,8 +360,8 @@ def main():
     fpe, fcounts = flops_per_event(args.proc, n_total_points, proc.n_hel)
     # the amplitude kernel skips the events left to the FP64 re-evaluation
     # (outside the timed interval): count only the events it evaluates
-    rescue = args.prec == "mixed" and args.proc != "ee_5a" and ng >= 3
-    n_rescued = rescued_events(mom_np) if rescue else 0
+    tau = proc.rescue_threshold if args.proc != "ee_5a" else 0.0
+    n_rescued = rescued_events(mom_np, tau) if tau > 0 and ng >= 3 else 0
     n_eval = args.n - n_rescued
     achieved = fpe * n_eval / (kms * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
@@ -397,7 +394,7 @@ def main():
                                 else "amplitude kernel (one event per wave)"),
                      "kernel_ms": kms,
                      "flops_per_event": fpe, "per_helicity_flops": fcounts["per_helicity_flops"],
-                     "events_evaluated": n_eval, "events_rescued_fp64": n_rescued,
+                     "events_evaluated": n_eval, "events_rescued_fp64": n_rescued, "rescue_tau": tau,
                      "counts": "algorithmic flops of the generated program (currents rebuilt per closing "
                                "group included) x the events the timed kernel evaluates",
                      "frac_executed": None if exec_ratio is None else exec_ratio * achieved / peak},

@@ -168,8 +168,11 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
  * which a gluon pair other than the two beams has |2 p_i.p_j| / s below
  * value * 1e-6 are evaluated a second time in FP64 and their results
  * replaced.  There the diagrams cancel strongly and single-precision
- * amplitudes lose up to about three more digits.  Default 3000 (3e-3) for
- * mixed-precision handles of those processes, 0 (off) otherwise; 0..1000000.
+ * amplitudes lose up to about three more digits.  Default for mixed-precision
+ * handles: 3000 (3e-3) for g g -> t tbar + 1..2 g, 1000 (1e-3) for
+ * g g -> t tbar g g g (about 2 % of its events; its FP64 pipeline costs four
+ * times the single-precision one), chosen from full-sample comparisons with
+ * the FP64 kernels; 0 (off) otherwise; 0..1000000.
  * Applies to mgrw_eval_me, mgrw_reweight and mgrw_reweight_kpoly.
  *
  * MGRW_OPT_COLOUR_MFMA (0 or 1; g g -> t tbar g g g): 1 forms the colour sum
@@ -188,6 +191,10 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
 enum { MGRW_OPT_LANE_MAPPING = 1, MGRW_OPT_RESCUE_PPM = 2, MGRW_OPT_KERNEL_TIMING = 3, MGRW_OPT_COLOUR_MFMA = 4 };
 enum { MGRW_MAP_AUTO = 0, MGRW_MAP_EVENT_PER_LANE = 1, MGRW_MAP_EVENT_PER_WAVE = 2 };
 mgrw_status mgrw_set_option(mgrw_process *p, int option, int64_t value);
+
+/* Current value of an option (as mgrw_set_option takes it) in *value.
+ * Errors: MGRW_ERR_ARG (null handle or value, unknown option). */
+mgrw_status mgrw_get_option(const mgrw_process *p, int option, int64_t *value);
 
 /* Device time in ms of the amplitude kernel(s) of the handle's most recent
  * launch (kernel timing on); waits for that launch to finish.  Errors:

@@ -122,6 +122,8 @@ def lib():
     L.mgrw_kernel_time_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.mgrw_kernel_time_ms.restype = ctypes.c_int
     L.mgrw_set_option.restype = ctypes.c_int
+    L.mgrw_get_option.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+    L.mgrw_get_option.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -220,6 +222,13 @@ class Process:
         """FP64 re-evaluation of events with a gluon invariant |2 p_i.p_j|/s < tau
         (mixed precision; 0 switches it off).  Stored in units of 1e-6."""
         check(lib().mgrw_set_option(self._h, 2, int(round(tau * 1e6))))
+
+    @property
+    def rescue_threshold(self):
+        """The FP64 re-evaluation threshold tau in force (0: off)."""
+        v = ctypes.c_int64()
+        check(lib().mgrw_get_option(self._h, 2, ctypes.byref(v)))
+        return v.value * 1e-6
 
     def _n(self, mom):
         if mom.dim() != 3 or mom.shape[0] != self.n_ext or mom.shape[1] != 4:

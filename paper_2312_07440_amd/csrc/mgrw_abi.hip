@@ -220,7 +220,10 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     p->base = *base;
     p->n_points = 0;
     p->mapping = MGRW_MAP_AUTO;
-    p->rescue_tau = (prec == MGRW_MIXED && proc >= MGRW_GG_TT && proc <= MGRW_GG_TTGGG) ? 3e-3 : 0.0;
+    // FP64 re-evaluation thresholds, from full-sample comparisons of mixed
+    // precision with the FP64 kernels (every weight within 1e-5)
+    p->rescue_tau = (prec == MGRW_MIXED && proc >= MGRW_GG_TT && proc <= MGRW_GG_TTGGG)
+                        ? (proc == MGRW_GG_TTGGG ? 1e-3 : 3e-3) : 0.0;
     p->sur = nullptr;
     p->t0 = p->t1 = nullptr;
     p->timed = 0;
@@ -329,6 +332,17 @@ mgrw_status mgrw_set_option(mgrw_process* p, int option, int64_t value) {
         return fail(MGRW_ERR_UNSUPPORTED, "g g -> t tbar g g g runs one event per wave only");
     p->mapping = int(value);
     return MGRW_OK;
+}
+
+mgrw_status mgrw_get_option(const mgrw_process* p, int option, int64_t* value) {
+    if (!p || !value) return fail(MGRW_ERR_ARG, "process or value is NULL");
+    switch (option) {
+        case MGRW_OPT_LANE_MAPPING: *value = p->mapping; return MGRW_OK;
+        case MGRW_OPT_RESCUE_PPM: *value = int64_t(p->rescue_tau * 1e6 + 0.5); return MGRW_OK;
+        case MGRW_OPT_KERNEL_TIMING: *value = p->t0 != nullptr; return MGRW_OK;
+        case MGRW_OPT_COLOUR_MFMA: *value = p->colour_mfma; return MGRW_OK;
+        default: return fail(MGRW_ERR_ARG, "unknown option");
+    }
 }
 
 mgrw_status mgrw_kernel_time_ms(mgrw_process* p, double* ms) {

@@ -158,3 +158,24 @@ def test_surrogate_needs_unit_base_kappa(L):
     st = (ctypes.c_double * 10)()
     assert L.mgrw_reweight_surrogate(p._h, None, None, 10, 0.01, 1, 0.01, None, st, None, None) == bd.ERR_UNSUPPORTED
     p.close()
+
+
+def test_get_option_and_default_rescue_thresholds(L):
+    """Options read back as set; the FP64 re-evaluation thresholds default to
+    3e-3 (g g -> t tbar g g), 1e-3 (g g -> t tbar g g g) and off in FP64."""
+    v = ctypes.c_int64()
+    for proc, prec, want in (("gg_ttgg", "mixed", 3000), ("gg_ttggg", "mixed", 1000), ("gg_ttgg", "fp64", 0),
+                             ("gg_tt", "mixed", 3000)):
+        p = bd.Process(proc, prec)
+        assert L.mgrw_get_option(p._h, 2, ctypes.byref(v)) == bd.OK
+        assert v.value == want
+        p.close()
+    p = bd.Process("gg_ttgg", "mixed")
+    assert L.mgrw_set_option(p._h, 2, 500) == bd.OK
+    assert p.rescue_threshold == pytest.approx(5e-4)
+    assert L.mgrw_get_option(p._h, 1, ctypes.byref(v)) == bd.OK and v.value == 0
+    assert L.mgrw_get_option(p._h, 99, ctypes.byref(v)) == bd.ERR_ARG
+    assert L.mgrw_get_option(p._h, 2, None) == bd.ERR_ARG
+    assert L.mgrw_get_option(None, 2, ctypes.byref(v)) == bd.ERR_ARG
+    p.close()
+

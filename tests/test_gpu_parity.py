@@ -273,6 +273,54 @@ def test_gg_ttggg_parity(torch_dev, n):
     assert e_w.max() <= TOL["mixed"]
 
 
+@pytest.mark.parametrize("n", [1, 70])
+def test_gg_ttggg_fp64_parity(torch_dev, n):
+    """g g -> t tbar g g g in FP64 (the program cut by closing-group chunk and
+    colour-flow range, J through device memory, double colour sum) against
+    the oracle at the FP64 bar, with input weights of both signs."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    mom, kap, w = qcd_case("gg_ttggg", n, seed_shift=900)
+    kap = kap[::4]
+    say(f"case gg_ttggg fp64 n={n}")
+    p = mg.Process("gg_ttggg", "fp64")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    out = p.reweight(to_dev(torch, mom), w_in=to_dev(torch, w), me_base_out=me0)
+    me3 = p.eval_me(to_dev(torch, mom), 2)
+    torch.cuda.synchronize()
+    me_ref, w_ref = oracle_qcd("gg_ttggg", mom, kap, w)
+    e_me, e_w = relerr(me0.cpu().numpy(), me_ref[0]), relerr(out.cpu().numpy(), w_ref)
+    e3 = relerr(me3.cpu().numpy(), me_ref[3])
+    say(f"  |M|^2 rel err max {e_me.max():.3e}; point 2 {e3.max():.3e}; W' rel err max {e_w.max():.3e}")
+    assert e_me.max() <= TOL["fp64"]
+    assert e3.max() <= TOL["fp64"]
+    assert e_w.max() <= TOL["fp64"]
+
+
+def test_gg_ttggg_fp64_batch_boundary(torch_dev):
+    """FP64 g g -> t tbar g g g over more events than one internal batch
+    (8192 at three points): events on both sides of the boundary and at the
+    ends against the oracle at the FP64 bar."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 8192 + 37
+    mom, kap, _ = qcd_case("gg_ttggg", n, seed_shift=7000)
+    kap = kap[::8]
+    say(f"case gg_ttggg fp64 batch boundary n={n}")
+    p = mg.Process("gg_ttggg", "fp64")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    out = p.reweight(to_dev(torch, mom)).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.isfinite(out).all()
+    idx = np.array([0, 1, 4000, 8190, 8191, 8192, 8193, n - 2, n - 1])
+    sub = np.ascontiguousarray(mom[:, :, idx])
+    _, w_ref = oracle_qcd("gg_ttggg", sub, kap, np.ones(len(idx)))
+    e = relerr(out[:, idx], w_ref)
+    say(f"  sampled W' rel err max {e.max():.3e}")
+    assert e.max() <= TOL["fp64"]
+
+
 def test_gg_ttggg_batch_boundary(torch_dev):
     """More events than one internal batch (8192): events on both sides of
     the boundary and at the ends, against the oracle."""

@@ -81,6 +81,43 @@ def test_every_mixed_weight_within_bar(torch_dev, name, n):
         assert emax <= TOL_MIXED
 
 
+@pytest.mark.timeout(900)
+def test_gg_ttggg_every_mixed_weight_within_bar(torch_dev):
+    """The full g g -> t tbar g g g workload (2^20 events in the seeded uneven
+    batches, 16 points): every mixed-precision weight and base |M|^2, with the
+    library's default re-evaluation threshold, against the FP64 pipeline.
+    Without the re-evaluation 4 events of this sample exceed 1e-5 (max
+    2.0e-5), all with a gluon invariant below 5.7e-4."""
+    import paper_2312_07440_amd as mg
+    from synth import uneven_batches
+    torch = torch_dev
+    n = 1 << 20
+    say(f"case full population gg_ttggg n={n}: generating")
+    mom_np = generate_events("gg_ttggg", n)
+    kap = kappa_points(16)
+    procs = {}
+    for prec in ("fp64", "mixed"):
+        procs[prec] = mg.Process("gg_ttggg", prec)
+        procs[prec].set_params([{"kappa_ttg": float(k)} for k in kap])
+    assert procs["mixed"].rescue_threshold == pytest.approx(1e-3)
+    emax, e0 = 0.0, 0
+    for s in uneven_batches("gg_ttggg", n):
+        mom = torch.from_numpy(np.ascontiguousarray(mom_np[:, :, e0:e0 + s])).to("cuda:0")
+        res = {}
+        for prec, p in procs.items():
+            me = torch.empty(s, dtype=torch.float64, device="cuda:0")
+            res[prec] = (p.reweight(mom, me_base_out=me), me)
+            torch.cuda.synchronize()
+        e = max((res["mixed"][0] / res["fp64"][0] - 1).abs().max().item(),
+                (res["mixed"][1] / res["fp64"][1] - 1).abs().max().item())
+        say(f"  batch [{e0}, {e0 + s}): max rel err {e:.3e}")
+        emax = max(emax, e)
+        e0 += s
+        del mom, res
+    say(f"  every weight: max rel err {emax:.3e}")
+    assert emax <= TOL_MIXED
+
+
 def test_rescue_replaces_only_flagged_events(torch_dev):
     import paper_2312_07440_amd as mg
     torch = torch_dev
@@ -101,6 +138,36 @@ def test_rescue_replaces_only_flagged_events(torch_dev):
     torch.cuda.synchronize()
     assert np.array_equal(outs["on"][:, ~fl], outs["off"][:, ~fl])
     assert np.abs(outs["on"][:, fl] / outs["fp64"][:, fl] - 1).max() <= 1e-12
+
+
+def test_gg_ttggg_rescue_replaces_only_flagged_events(torch_dev):
+    """g g -> t tbar g g g, mixed precision: the listed events go through the
+    double-precision (chunk, flow range) pipeline, which takes list positions
+    as slots; they then equal the FP64 call to 1e-12 and every other event is
+    bit-identical to the call with the re-evaluation off."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 3000
+    mom_np = generate_events("gg_ttggg", n, first_event=4242)
+    fl = flagged(mom_np, TAU)
+    say(f"case rescue selection gg_ttggg n={n}: {fl.sum()} flagged")
+    assert 0 < fl.sum() < n
+    mom = torch.from_numpy(mom_np).to("cuda:0")
+    kap = kappa_points(4)
+    outs = {}
+    for label, prec, tau in (("off", "mixed", 0.0), ("on", "mixed", TAU), ("fp64", "fp64", None)):
+        say(f"  {label}")
+        p = mg.Process("gg_ttggg", prec)
+        p.set_params([{"kappa_ttg": float(k)} for k in kap])
+        if tau is not None:
+            p.set_rescue_threshold(tau)
+        me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        outs[label] = (p.reweight(mom, me_base_out=me0).cpu().numpy(), me0.cpu().numpy())
+    torch.cuda.synchronize()
+    assert np.array_equal(outs["on"][0][:, ~fl], outs["off"][0][:, ~fl])
+    assert np.array_equal(outs["on"][1][~fl], outs["off"][1][~fl])
+    assert np.abs(outs["on"][0][:, fl] / outs["fp64"][0][:, fl] - 1).max() <= 1e-12
+    assert np.abs(outs["on"][1][fl] / outs["fp64"][1][fl] - 1).max() <= 1e-12
 
 
 def test_rescue_applies_to_eval_me(torch_dev):
@@ -124,7 +191,8 @@ def test_rescue_option_errors(torch_dev):
     with pytest.raises(RuntimeError, match="rescue"):
         mg.Process("gg_ttgg", "fp64").set_rescue_threshold(1e-3)
     with pytest.raises(RuntimeError, match="rescue"):
-        mg.Process("gg_ttggg", "mixed").set_rescue_threshold(1e-3)
+        mg.Process("gg_ttggg", "fp64").set_rescue_threshold(1e-3)
+    mg.Process("gg_ttggg", "mixed").set_rescue_threshold(1e-3)
     with pytest.raises(RuntimeError, match="ppm"):
         mg.Process("gg_ttgg", "mixed").set_rescue_threshold(2.0)
     mg.Process("gg_ttgg", "fp64").set_rescue_threshold(0.0)
