@@ -124,6 +124,25 @@ mgrw_status mgrw_eval_me(mgrw_process *p, const double *mom, int64_t n_events, i
 mgrw_status mgrw_reweight(mgrw_process *p, const double *mom, const double *w_in, int64_t n_events,
                           double *w_out, double *me_base_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as mgrw_reweight, bit for bit, without any allocation.  The
+ * per-event kinematics records and the list of events for the FP64
+ * re-evaluation come from a 256 MiB device array inside the library (one per
+ * GPU, held until the process ends); the events run in chunks whose buffers
+ * fit it (about 2.5e5 events per chunk for g g -> t tbar g g).  The call
+ * allocates nothing and records no kernel timing (mgrw_kernel_time_ms then
+ * reports MGRW_ERR_STATE).  Every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other threads, other handles)
+ * race and must be serialised by the caller; nothing from a previous call is
+ * read.  The stream must belong to the current device.
+ * Errors: as mgrw_reweight; MGRW_ERR_UNSUPPORTED for g g -> t tbar g g g (its
+ * colour-flow buffers, about 2 MB per event, exceed the array) and device
+ * ordinals above 63; MGRW_ERR_ARG for a stream of another device;
+ * MGRW_ERR_DEVICE if the array's address cannot be obtained. */
+mgrw_status mgrw_reweight_noalloc(mgrw_process *p, const double *mom, const double *w_in, int64_t n_events,
+                                  double *w_out, double *me_base_out, void *stream);
+
 /* mgrw_reweight for events and weights in HOST memory (procedure steps 2-8
  * with the transfers, which dominate small samples: Sec. 3.3).  mom
  * ([n_ext][4][n_events]), w_in ([n_events], may be NULL), w_out

@@ -124,6 +124,8 @@ def lib():
     L.mgrw_set_option.restype = ctypes.c_int
     L.mgrw_get_option.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
     L.mgrw_get_option.restype = ctypes.c_int
+    L.mgrw_reweight_noalloc.argtypes = [vp, dp, dp, i64, dp, dp, vp]
+    L.mgrw_reweight_noalloc.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -251,6 +253,18 @@ class Process:
         check(lib().mgrw_reweight(self._h, _ptr(mom, "mom"), _ptr(w_in, "w_in", n, allow_none=True), n,
                                   _ptr(out, "out", self.n_points * n),
                                   _ptr(me_base_out, "me_base_out", n, allow_none=True), _stream(stream)))
+        return out
+
+    def reweight_noalloc(self, mom, w_in=None, out=None, me_base_out=None, stream=None):
+        """mgrw_reweight_noalloc: mgrw_reweight without any device allocation
+        inside the library (`out` is allocated here when not given)."""
+        import torch
+        n = self._n(mom)
+        if out is None:
+            out = torch.empty((self.n_points, n), dtype=torch.float64, device=mom.device)
+        check(lib().mgrw_reweight_noalloc(self._h, _ptr(mom, "mom"), _ptr(w_in, "w_in", n, allow_none=True), n,
+                                          _ptr(out, "out", self.n_points * n),
+                                          _ptr(me_base_out, "me_base_out", n, allow_none=True), _stream(stream)))
         return out
 
     def reweight_host(self, mom, w_in=None, chunk=0, me_base=False, out=None):

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -132,11 +133,15 @@ mgrw_status launched(hipError_t err) {
     return MGRW_OK;
 }
 
-// Shared body of eval_me (mode 1, one point) and reweight (mode 0).
+// Shared body of eval_me (mode 1, one point) and reweight (mode 0).  With a
+// scratch span the launch allocates nothing (its buffers come from the span)
+// and records no kernel timing.
 mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t n, const mgrw_params* pts,
-                int npts, int mode, double* out, double* me0, void* stream, int kpoly = 0) {
+                int npts, int mode, double* out, double* me0, void* stream, int kpoly = 0,
+                scratch_span sc = {nullptr, 0}) {
     if (n < 0) return fail(MGRW_ERR_ARG, "n_events < 0");
     if (n == 0) return MGRW_OK;
+    const hipEvent_t t0 = sc.ptr ? nullptr : p->t0, t1 = sc.ptr ? nullptr : p->t1;
     mgrw_status st;
     if ((st = check_device_ptr(mom, "mom", false)) != MGRW_OK) return st;
     if ((st = check_device_ptr(out, mode == 1 ? "me_out" : "w_out", false)) != MGRW_OK) return st;
@@ -150,9 +155,10 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
         a.npts = npts;
         a.mode = mode;
         a.kpoly = kpoly;
-        a.t0 = p->t0;
-        a.t1 = p->t1;
-        p->timed = p->t0 != nullptr;
+        a.t0 = t0;
+        a.t1 = t1;
+        a.scratch = sc;
+        p->timed = t0 != nullptr;
         if ((n + 3) / 4 > 0x7fffffffLL) return fail(MGRW_ERR_ARG, "n_events too large for one launch");
         return launched(launch_ee5a(p->prec == MGRW_FP64, mom, w_in, n, a, out, me0, s));
     }
@@ -185,9 +191,10 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
     a.kpoly = kpoly;
     a.rescue_tau = p->rescue_tau;
     a.colour_mfma = p->colour_mfma;
-    a.t0 = p->t0;
-    a.t1 = p->t1;
-    p->timed = p->t0 != nullptr;
+    a.t0 = t0;
+    a.t1 = t1;
+    a.scratch = sc;
+    p->timed = t0 != nullptr;
     const int fp64 = p->prec == MGRW_FP64;
     switch (p->proc) {
         case MGRW_GG_TT: return launched(launch_gg_tt(fp64, mom, w_in, n, a, out, me0, s));
@@ -198,9 +205,67 @@ mgrw_status run(mgrw_process* p, const double* mom, const double* w_in, int64_t 
     }
 }
 
+// ------------------------------------------- allocation-free reweighting
+//
+// mgrw_reweight_noalloc takes every intermediate buffer of a launch (per-event
+// kinematics records, the list of events for the FP64 re-evaluation) from
+// this file-scope device array instead of allocating; the events run in
+// chunks whose buffers fit.  Each GPU holds its own copy at its own address,
+// looked up once per device with that device current.  In host code the
+// array's name is only a handle for that lookup, never a device address.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch span of the device the stream belongs to (the current device
+// for the null stream), which must be the current device.
+mgrw_status device_scratch(hipStream_t s, scratch_span* out) {
+    int dev = -1;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return fail(MGRW_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(err));
+    if (s) {
+        hipDevice_t sd = -1;
+        err = hipStreamGetDevice(s, &sd);
+        if (err != hipSuccess) return fail(MGRW_ERR_ARG, std::string("stream: ") + hipGetErrorString(err));
+        if (sd != dev) return fail(MGRW_ERR_ARG, "stream belongs to another device than the current one");
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(MGRW_ERR_UNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (err != hipSuccess || !ptr)
+            return fail(MGRW_ERR_DEVICE, std::string("scratch address: ") + hipGetErrorString(err));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = {g_scratch_ptr[dev], kScratchBytes};
+    return MGRW_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+mgrw_status mgrw_reweight_noalloc(mgrw_process* p, const double* mom, const double* w_in, int64_t n_events,
+                                  double* w_out, double* me_base_out, void* stream) {
+    if (!p) return fail(MGRW_ERR_ARG, "process is NULL");
+    if (p->n_points == 0) return fail(MGRW_ERR_STATE, "no parameter points set");
+    if (p->proc == MGRW_GG_TTGGG)
+        return fail(MGRW_ERR_UNSUPPORTED,
+                    "allocation-free reweight: g g -> t tbar g g g needs colour-flow buffers of about 2 MB per "
+                    "event, beyond the 256 MiB scratch; use mgrw_reweight");
+    if (n_events <= 0) return run(p, mom, w_in, n_events, nullptr, 0, 0, w_out, me_base_out, stream);
+    scratch_span sc;
+    mgrw_status st = device_scratch(static_cast<hipStream_t>(stream), &sc);
+    if (st != MGRW_OK) return st;
+    mgrw_params all[kMaxLaunchPoints];
+    all[0] = p->base;
+    for (int k = 0; k < p->n_points; ++k) all[k + 1] = p->points[k];
+    return run(p, mom, w_in, n_events, all, p->n_points + 1, 0, w_out, me_base_out, stream, 0, sc);
+}
 
 mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgrw_process** out) {
     if (!out) return fail(MGRW_ERR_ARG, "out is NULL");

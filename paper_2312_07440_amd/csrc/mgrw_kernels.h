@@ -15,6 +15,25 @@ namespace mgrw {
 constexpr int kBlock = 256;
 constexpr int kMaxLaunchPoints = MGRW_MAX_POINTS + 1;   // base + new points
 
+// Device memory a launch may use for its intermediate buffers instead of
+// allocating them.  ptr == nullptr: the launch allocates (stream-ordered).
+// Otherwise the buffers are carved from [ptr, ptr + bytes) (ptr 256-byte
+// aligned) and the events are processed in chunks whose buffers fit.
+struct scratch_span {
+    void* ptr;
+    size_t bytes;
+};
+
+// Events per chunk when each event needs per_event bytes of scratch and the
+// chunk a fixed head of head bytes (0 if not even one event fits).
+inline int64_t scratch_chunk(const scratch_span& sc, size_t per_event, size_t head) {
+    if (sc.bytes <= head || per_event == 0) return 0;
+    return int64_t((sc.bytes - head) / per_event);
+}
+
+// Round up to the 256-byte alignment of every carved buffer.
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
 // Parameters travel by value with each launch (kernel-argument segment), so a
 // later mgrw_set_params never races with work already queued.
 struct qcd_launch {
@@ -27,6 +46,7 @@ struct qcd_launch {
     double rescue_tau;   // > 0: events with a gluon invariant |2 p_i.p_j|/s below it are redone in FP64
     hipEvent_t t0, t1;   // non-null: recorded around the amplitude kernel(s) of the launch
     int colour_mfma;     // split programs: colour sum on the matrix cores (after the last part)
+    scratch_span scratch;   // non-null: caller-provided device scratch (no allocation; events in chunks)
 };
 
 struct ew_launch {
@@ -42,6 +62,7 @@ struct qed_launch {
     int mode;
     int kpoly;       // 1: one evaluation at e = 1, |M|^2 = e^(2n) |M_1|^2 for every point
     hipEvent_t t0, t1;
+    scratch_span scratch;
 };
 
 // Device-side timestamps around the amplitude kernel(s) of a launch.
@@ -188,22 +209,26 @@ struct event_data {
 
 // Kinematics and wavefunction bases of every event; with tau > 0 also lists
 // the ill-conditioned events (count, list) and marks them to be skipped.
+// Events e0 .. e0 + nb - 1 of the n in mom; record el holds event e0 + el and
+// the list holds event numbers.
 template <class Proc, typename T>
 __global__ void __launch_bounds__(kBlock)
-qcd_setup_kernel(const double* __restrict__ mom, int64_t n, double mt, event_data<Proc, T>* __restrict__ ev,
-                 double tau, unsigned long long* __restrict__ count, int64_t* __restrict__ list) {
-    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (e >= n) return;
+qcd_setup_kernel(const double* __restrict__ mom, int64_t n, int64_t e0, int64_t nb, double mt,
+                 event_data<Proc, T>* __restrict__ ev, double tau, unsigned long long* __restrict__ count,
+                 int64_t* __restrict__ list) {
+    const int64_t el = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (el >= nb) return;
+    const int64_t e = e0 + el;
     double p[Proc::NEXT][4];
     load_event<Proc::NEXT>(mom, n, e, p);
-    Proc::kinematics(p, mt, ev[e].k);
-    Proc::external_basis(p, mt, ev[e].b);
+    Proc::kinematics(p, mt, ev[el].k);
+    Proc::external_basis(p, mt, ev[el].b);
     int skip = 0;
     if (tau > 0.0 && ill_conditioned<Proc>(p, tau)) {
         skip = 1;
         list[atomicAdd(count, 1ull)] = e;
     }
-    ev[e].skip = skip;
+    ev[el].skip = skip;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -212,16 +237,18 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Events e0 .. e0 + nb - 1 (record el = event e0 + el).
 template <class Proc, typename T>
 __global__ void __launch_bounds__(kBlock, MGRW_WAVE_WPE)
-qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* __restrict__ w_in, int64_t n,
-                qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
+qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t nb, const double* __restrict__ w_in,
+                int64_t n, qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
     static_assert(Proc::NHEL % 64 == 0, "helicity configurations must fill whole waves");
-    const int64_t e = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (e >= n || ev[e].skip) return;   // whole wave; no barriers below
+    const int64_t el = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (el >= nb || ev[el].skip) return;   // whole wave; no barriers below
+    const int64_t e = e0 + el;
     const int lane = threadIdx.x & 63;
-    const typename Proc::template kin<T>& k = ev[e].k;
-    const typename Proc::template basis<T>& b = ev[e].b;
+    const typename Proc::template kin<T>& k = ev[el].k;
+    const typename Proc::template basis<T>& b = ev[el].b;
     const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
     double me0 = 0.0;
 #pragma unroll 1
@@ -318,10 +345,12 @@ constexpr bool kpoly_lds_split() {
 // One event per wave, helicity configurations on the lanes.
 template <class Proc, typename T>
 __global__ void __launch_bounds__(kBlock)
-qcd_kpoly_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* __restrict__ w_in, int64_t n,
-                      qcd_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
-    const int64_t e = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (e >= n || ev[e].skip) return;   // whole wave
+qcd_kpoly_wave_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t nb,
+                      const double* __restrict__ w_in, int64_t n, qcd_launch a, double* __restrict__ out,
+                      double* __restrict__ me0_out) {
+    const int64_t el = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (el >= nb || ev[el].skip) return;   // whole wave
+    const int64_t e = e0 + el;
     const int lane = threadIdx.x & 63;
     double B[kpoly_pairs<Proc>()] = {};
 #pragma unroll 1
@@ -333,8 +362,8 @@ qcd_kpoly_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* 
             split_acc<T, N, NL, kBlock> acc{&jl[threadIdx.x]};
             typename Proc::template ext<T> w;
             typename Proc::template coup<T> c = {T(1), T(1), T(1)};
-            Proc::template external<T>(ev[e].b, hc + lane, w);
-            Proc::amplitude_kpoly(w, ev[e].k, c, acc);
+            Proc::template external<T>(ev[el].b, hc + lane, w);
+            Proc::amplitude_kpoly(w, ev[el].k, c, acc);
             cx<T> J[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) J[i] = acc[i];
@@ -344,9 +373,9 @@ qcd_kpoly_wave_kernel(const event_data<Proc, T>* __restrict__ ev, const double* 
             // slot, as in qcd_wave_kernel (10 % faster for g g -> t tbar g g;
             // in single precision registers are faster)
             __shared__ lds_slot<typename Proc::template ext<T>> wfs[kBlock];
-            kpoly_helicity<Proc, T>(ev[e].k, ev[e].b, hc + lane, B, wfs[threadIdx.x].v);
+            kpoly_helicity<Proc, T>(ev[el].k, ev[el].b, hc + lane, B, wfs[threadIdx.x].v);
         } else {
-            kpoly_helicity<Proc, T>(ev[e].k, ev[e].b, hc + lane, B);
+            kpoly_helicity<Proc, T>(ev[el].k, ev[el].b, hc + lane, B);
         }
     }
 #pragma unroll
@@ -368,12 +397,14 @@ __global__ void rescue_reset_kernel(unsigned long long* count) {
     if (blockIdx.x == 0 && threadIdx.x == 0) count[0] = 0;
 }
 
+// Events e0 .. e0 + nb - 1 of the n in mom.
 template <class Proc>
 __global__ void __launch_bounds__(kBlock)
-rescue_flag_kernel(const double* __restrict__ mom, int64_t n, double tau, unsigned long long* __restrict__ count,
-                   int64_t* __restrict__ list) {
-    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (e >= n) return;
+rescue_flag_kernel(const double* __restrict__ mom, int64_t n, int64_t e0, int64_t nb, double tau,
+                   unsigned long long* __restrict__ count, int64_t* __restrict__ list) {
+    const int64_t el = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (el >= nb) return;
+    const int64_t e = e0 + el;
     double p[Proc::NEXT][4];
     load_event<Proc::NEXT>(mom, n, e, p);
     if (ill_conditioned<Proc>(p, tau)) list[atomicAdd(count, 1ull)] = e;
@@ -453,6 +484,9 @@ qcd_rescue_kernel(const double* __restrict__ mom, const int64_t* __restrict__ li
 
 constexpr unsigned kRescueBlocks = 1024;
 
+// The FP64 re-evaluation after a one-event-per-lane pass: list the
+// ill-conditioned events, then redo them.  With a scratch span the count and
+// list live there and the events are flagged and redone chunk by chunk.
 template <class Proc>
 hipError_t launch_rescue(const double* mom, const double* w_in, int64_t n, const qcd_launch& a, double* out,
                          double* me0, hipStream_t s) {
@@ -460,21 +494,32 @@ hipError_t launch_rescue(const double* mom, const double* w_in, int64_t n, const
         return hipSuccess;   // no final-state gluon
     } else {
         int64_t* buf = nullptr;
-        hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&buf), sizeof(int64_t) * size_t(n + 1), s);
-        if (err != hipSuccess) return err;
+        int64_t chunk = n;
+        if (a.scratch.ptr) {
+            chunk = scratch_chunk(a.scratch, sizeof(int64_t), 256);
+            if (chunk < 1) return hipErrorInvalidValue;
+            buf = static_cast<int64_t*>(a.scratch.ptr);
+        } else {
+            hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&buf), sizeof(int64_t) * size_t(n + 1), s);
+            if (err != hipSuccess) return err;
+        }
         unsigned long long* count = reinterpret_cast<unsigned long long*>(buf);
-        int64_t* list = buf + 1;
-        hipLaunchKernelGGL((rescue_reset_kernel<Proc>), dim3(1), dim3(64), 0, s, count);
-        hipLaunchKernelGGL((rescue_flag_kernel<Proc>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           mom, n, a.rescue_tau, count, list);
-        if (a.kpoly)
-            hipLaunchKernelGGL((qcd_rescue_kernel<Proc, true>), dim3(kRescueBlocks), dim3(kBlock), 0, s, mom, list,
-                               count, w_in, n, a, out, me0);
-        else
-            hipLaunchKernelGGL((qcd_rescue_kernel<Proc, false>), dim3(kRescueBlocks), dim3(kBlock), 0, s, mom, list,
-                               count, w_in, n, a, out, me0);
-        err = hipGetLastError();
-        hipError_t ferr = hipFreeAsync(buf, s);
+        int64_t* list = a.scratch.ptr ? buf + 32 : buf + 1;   // after the 256-byte head in a scratch span
+        hipError_t err = hipSuccess;
+        for (int64_t e0 = 0; e0 < n && err == hipSuccess; e0 += chunk) {
+            const int64_t nb = n - e0 < chunk ? n - e0 : chunk;
+            hipLaunchKernelGGL((rescue_reset_kernel<Proc>), dim3(1), dim3(64), 0, s, count);
+            hipLaunchKernelGGL((rescue_flag_kernel<Proc>), dim3(unsigned((nb + kBlock - 1) / kBlock)), dim3(kBlock),
+                               0, s, mom, n, e0, nb, a.rescue_tau, count, list);
+            if (a.kpoly)
+                hipLaunchKernelGGL((qcd_rescue_kernel<Proc, true>), dim3(kRescueBlocks), dim3(kBlock), 0, s, mom,
+                                   list, count, w_in, n, a, out, me0);
+            else
+                hipLaunchKernelGGL((qcd_rescue_kernel<Proc, false>), dim3(kRescueBlocks), dim3(kBlock), 0, s, mom,
+                                   list, count, w_in, n, a, out, me0);
+            err = hipGetLastError();
+        }
+        hipError_t ferr = a.scratch.ptr ? hipSuccess : hipFreeAsync(buf, s);
         return err != hipSuccess ? err : ferr;
     }
 }
@@ -482,38 +527,60 @@ hipError_t launch_rescue(const double* mom, const double* w_in, int64_t n, const
 // One event per wave: per-event data (in single precision with the rescue
 // on, also the list of ill-conditioned events, which the amplitude kernel
 // skips), the amplitude kernel, then the FP64 re-evaluation of the listed
-// events.  KP: kappa-polynomial evaluation.
+// events.  KP: kappa-polynomial evaluation.  Without a scratch span the
+// buffers are stream-ordered allocations for all n events; with one they are
+// carved from it (records, then count and list) and the events run in chunks
+// whose buffers fit.
 template <class Proc, typename T, bool KP>
 hipError_t launch_wave_pipeline(const double* mom, const double* w_in, int64_t n, const qcd_launch& a, double* out,
                                 double* me0, hipStream_t s) {
     const bool rescue = sizeof(T) == 4 && a.rescue_tau > 0.0 && Proc::NEXT > 4;
-    event_data<Proc, T>* ev = nullptr;
-    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(event_data<Proc, T>) * size_t(n), s);
-    if (err != hipSuccess) return err;
+    using ED = event_data<Proc, T>;
+    ED* ev = nullptr;
     int64_t* buf = nullptr;
-    if (rescue) {
-        err = hipMallocAsync(reinterpret_cast<void**>(&buf), sizeof(int64_t) * size_t(n + 1), s);
-        if (err != hipSuccess) {
-            (void)hipFreeAsync(ev, s);
-            return err;
+    int64_t chunk = n;
+    if (a.scratch.ptr) {
+        // per event: one record and (rescue) one list entry; head: the count
+        // word and the alignment of the list
+        chunk = scratch_chunk(a.scratch, sizeof(ED) + (rescue ? sizeof(int64_t) : 0), 512);
+        if (chunk < 1) return hipErrorInvalidValue;
+        ev = static_cast<ED*>(a.scratch.ptr);
+        if (rescue)
+            buf = reinterpret_cast<int64_t*>(static_cast<char*>(a.scratch.ptr) + align256(sizeof(ED) * size_t(chunk)));
+    } else {
+        hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(ED) * size_t(n), s);
+        if (err != hipSuccess) return err;
+        if (rescue) {
+            err = hipMallocAsync(reinterpret_cast<void**>(&buf), sizeof(int64_t) * size_t(n + 1), s);
+            if (err != hipSuccess) {
+                (void)hipFreeAsync(ev, s);
+                return err;
+            }
         }
     }
     unsigned long long* count = rescue ? reinterpret_cast<unsigned long long*>(buf) : nullptr;
     int64_t* list = rescue ? buf + 1 : nullptr;
-    if (rescue) hipLaunchKernelGGL((rescue_reset_kernel<Proc>), dim3(1), dim3(64), 0, s, count);
-    hipLaunchKernelGGL((qcd_setup_kernel<Proc, T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       mom, n, a.mt, ev, rescue ? a.rescue_tau : 0.0, count, list);
-    const dim3 grid(unsigned((n + kBlock / 64 - 1) / (kBlock / 64)));
-    mark(a.t0, s);
-    if constexpr (KP)
-        hipLaunchKernelGGL((qcd_kpoly_wave_kernel<Proc, T>), grid, dim3(kBlock), 0, s, ev, w_in, n, a, out, me0);
-    else
-        hipLaunchKernelGGL((qcd_wave_kernel<Proc, T>), grid, dim3(kBlock), 0, s, ev, w_in, n, a, out, me0);
-    mark(a.t1, s);
-    if (rescue)
-        hipLaunchKernelGGL((qcd_rescue_kernel<Proc, KP>), dim3(kRescueBlocks), dim3(kBlock), 0, s, mom, list, count,
-                           w_in, n, a, out, me0);
-    err = hipGetLastError();
+    hipError_t err = hipSuccess;
+    for (int64_t e0 = 0; e0 < n && err == hipSuccess; e0 += chunk) {
+        const int64_t nb = n - e0 < chunk ? n - e0 : chunk;
+        if (rescue) hipLaunchKernelGGL((rescue_reset_kernel<Proc>), dim3(1), dim3(64), 0, s, count);
+        hipLaunchKernelGGL((qcd_setup_kernel<Proc, T>), dim3(unsigned((nb + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, mom, n, e0, nb, a.mt, ev, rescue ? a.rescue_tau : 0.0, count, list);
+        const dim3 grid(unsigned((nb + kBlock / 64 - 1) / (kBlock / 64)));
+        mark(a.t0, s);
+        if constexpr (KP)
+            hipLaunchKernelGGL((qcd_kpoly_wave_kernel<Proc, T>), grid, dim3(kBlock), 0, s, ev, e0, nb, w_in, n, a,
+                               out, me0);
+        else
+            hipLaunchKernelGGL((qcd_wave_kernel<Proc, T>), grid, dim3(kBlock), 0, s, ev, e0, nb, w_in, n, a, out,
+                               me0);
+        mark(a.t1, s);
+        if (rescue)
+            hipLaunchKernelGGL((qcd_rescue_kernel<Proc, KP>), dim3(kRescueBlocks), dim3(kBlock), 0, s, mom, list,
+                               count, w_in, n, a, out, me0);
+        err = hipGetLastError();
+    }
+    if (a.scratch.ptr) return err;
     hipError_t f1 = rescue ? hipFreeAsync(buf, s) : hipSuccess;
     hipError_t f2 = hipFreeAsync(ev, s);
     return err != hipSuccess ? err : (f1 != hipSuccess ? f1 : f2);
@@ -982,6 +1049,7 @@ hipError_t launch_split64(const split_launchers<Proc>& L, const double* mom, int
 template <class Proc>
 hipError_t launch_split(const split_launchers<Proc>& L, int fp64, const double* mom, const double* w_in, int64_t n,
                         const qcd_launch& a, double* out, double* me0, hipStream_t s) {
+    if (a.scratch.ptr) return hipErrorNotSupported;   // J buffers of MBs per event: always allocated
     if (fp64) return launch_split64<Proc>(L, mom, n, nullptr, nullptr, n, w_in, a, out, me0, s, true);
     using ED = event_data<Proc, float>;
     const bool rescue = a.rescue_tau > 0.0;
@@ -1004,7 +1072,7 @@ hipError_t launch_split(const split_launchers<Proc>& L, int fp64, const double* 
     int64_t* list = rescue ? buf + 1 : nullptr;
     if (rescue) hipLaunchKernelGGL((rescue_reset_kernel<Proc>), dim3(1), dim3(64), 0, s, count);
     hipLaunchKernelGGL((qcd_setup_kernel<Proc, float>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       mom, n, a.mt, ev, rescue ? a.rescue_tau : 0.0, count, list);
+                       mom, n, int64_t(0), n, a.mt, ev, rescue ? a.rescue_tau : 0.0, count, list);
     err = hipGetLastError();
     mark(a.t0, s);
     for (int64_t e0 = 0; e0 < n && err == hipSuccess; e0 += B) {

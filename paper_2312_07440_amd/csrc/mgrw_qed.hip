@@ -13,25 +13,28 @@ namespace mgrw {
 
 namespace {
 
+// Events e0 .. e0 + nb - 1 of the n in mom; record el holds event e0 + el.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-ee5a_setup_kernel(const double* __restrict__ mom, int64_t n, ee_5a::event<T>* __restrict__ ev) {
-    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (e >= n) return;
+ee5a_setup_kernel(const double* __restrict__ mom, int64_t n, int64_t e0, int64_t nb,
+                  ee_5a::event<T>* __restrict__ ev) {
+    const int64_t el = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (el >= nb) return;
     double p[ee_5a::NEXT][4];
-    load_event<ee_5a::NEXT>(mom, n, e, p);
-    ee_5a::setup(p, ev[e]);
+    load_event<ee_5a::NEXT>(mom, n, e0 + el, p);
+    ee_5a::setup(p, ev[el]);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-ee5a_wave_kernel(const ee_5a::event<T>* __restrict__ ev, const double* __restrict__ w_in, int64_t n, qed_launch a,
-                 double* __restrict__ out, double* __restrict__ me0_out) {
+ee5a_wave_kernel(const ee_5a::event<T>* __restrict__ ev, int64_t e0, int64_t nb, const double* __restrict__ w_in,
+                 int64_t n, qed_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
     static_assert(ee_5a::NLIVE == 64, "one live helicity configuration per lane");
-    const int64_t e = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (e >= n) return;   // whole wave; no barriers below
+    const int64_t el = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (el >= nb) return;   // whole wave; no barriers below
+    const int64_t e = e0 + el;
     const int lane = threadIdx.x & 63;
-    const ee_5a::event<T>& d = ev[e];
+    const ee_5a::event<T>& d = ev[el];
     const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
     const double scale = d.flux * ee_5a::NORM;
     double me0 = 0.0;
@@ -65,19 +68,33 @@ ee5a_wave_kernel(const ee_5a::event<T>* __restrict__ ev, const double* __restric
     }
 }
 
+// Per-event records: a stream-ordered allocation for all n events, or (with
+// a scratch span) carved from it, the events then run in chunks that fit.
 template <typename T>
 hipError_t launch(const double* mom, const double* w_in, int64_t n, const qed_launch& a, double* out, double* me0,
                   hipStream_t s) {
     ee_5a::event<T>* ev = nullptr;
-    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(ee_5a::event<T>) * size_t(n), s);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((ee5a_setup_kernel<T>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, mom,
-                       n, ev);
-    mark(a.t0, s);
-    hipLaunchKernelGGL((ee5a_wave_kernel<T>), dim3(unsigned((n + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
-                       s, ev, w_in, n, a, out, me0);
-    mark(a.t1, s);
-    err = hipGetLastError();
+    int64_t chunk = n;
+    if (a.scratch.ptr) {
+        chunk = scratch_chunk(a.scratch, sizeof(ee_5a::event<T>), 0);
+        if (chunk < 1) return hipErrorInvalidValue;
+        ev = static_cast<ee_5a::event<T>*>(a.scratch.ptr);
+    } else {
+        hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&ev), sizeof(ee_5a::event<T>) * size_t(n), s);
+        if (err != hipSuccess) return err;
+    }
+    hipError_t err = hipSuccess;
+    for (int64_t e0 = 0; e0 < n && err == hipSuccess; e0 += chunk) {
+        const int64_t nb = n - e0 < chunk ? n - e0 : chunk;
+        hipLaunchKernelGGL((ee5a_setup_kernel<T>), dim3(unsigned((nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           mom, n, e0, nb, ev);
+        mark(a.t0, s);
+        hipLaunchKernelGGL((ee5a_wave_kernel<T>), dim3(unsigned((nb + kBlock / 64 - 1) / (kBlock / 64))),
+                           dim3(kBlock), 0, s, ev, e0, nb, w_in, n, a, out, me0);
+        mark(a.t1, s);
+        err = hipGetLastError();
+    }
+    if (a.scratch.ptr) return err;
     hipError_t ferr = hipFreeAsync(ev, s);
     return err != hipSuccess ? err : ferr;
 }

@@ -179,3 +179,19 @@ def test_get_option_and_default_rescue_thresholds(L):
     assert L.mgrw_get_option(None, 2, ctypes.byref(v)) == bd.ERR_ARG
     p.close()
 
+
+def test_noalloc_argument_errors(L):
+    """mgrw_reweight_noalloc checks its arguments like mgrw_reweight, before
+    touching the device, and refuses the split program."""
+    assert L.mgrw_reweight_noalloc(None, None, None, 10, None, None, None) == bd.ERR_ARG
+    p = bd.Process("gg_ttgg", "mixed")
+    assert L.mgrw_reweight_noalloc(p._h, None, None, 10, None, None, None) == bd.ERR_STATE
+    p.set_params([{"kappa_ttg": 1.1}])
+    assert L.mgrw_reweight_noalloc(p._h, None, None, -1, None, None, None) == bd.ERR_ARG
+    assert L.mgrw_reweight_noalloc(p._h, None, None, 0, None, None, None) == bd.OK
+    p.close()
+    q = bd.Process("gg_ttggg", "mixed")
+    q.set_params([{"kappa_ttg": 1.1}])
+    assert L.mgrw_reweight_noalloc(q._h, None, None, 10, None, None, None) == bd.ERR_UNSUPPORTED
+    assert b"g g -> t tbar g g g" in L.mgrw_last_error()
+    q.close()
