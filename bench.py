@@ -127,38 +127,68 @@ def cpu_baseline(proc, ng, mom_np, kap, gpu_out, sample, points_per_event):
         float(err.max()), float(np.median(err))
 
 
-def surrogate_leg(args, proc, mom, exact_out, kap, torch, generate_events):
-    """Train the MLP on disjoint events, then time the audited surrogate
-    reweight of the same batch; error measured against the exact weights."""
+def surrogate_leg(args, proc, mom, exact_out, kap, torch, generate_events, exact_ms, kpoly_ms):
+    """Train the MLP on disjoint events (labels from the exact kernels), then
+    time the audited surrogate reweight of the same batch; error measured
+    against the exact weights.  Also: the time per batch with the training
+    included, the number of batches after which the training has paid for
+    itself against each exact path, and the same network fitted to the 25
+    inputs of the workload's definition (momenta and kappa only)."""
     log(f"surrogate: generating {args.train_events} training events")
     train = torch.from_numpy(generate_events(args.proc, args.train_events, first_event=1 << 26)).to(mom.device)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    losses = proc.train_surrogate(train, epochs=args.epochs, batch=16384, lr=2e-3, lr_decay=0.7, seed=3003)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    log(f"surrogate: trained in {t_train:.1f}s, losses {losses}")
-    del train
-    sout = torch.empty_like(exact_out)
-    proc.reweight_surrogate(mom, out=sout, audit_fraction=args.audit, seed=7, max_audit_error=1.0)
-    torch.cuda.synchronize()
-    times, stats, fb = [], None, False
-    for i in range(args.steps):
-        t0 = time.perf_counter()
-        _, stats, fb = proc.reweight_surrogate(mom, out=sout, audit_fraction=args.audit, seed=7 + i,
-                                               max_audit_error=0.01)
+
+    def fit():
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    ms = 1e3 * float(np.mean(times))
-    err = torch.abs(sout / exact_out - 1.0)
+        t0 = time.perf_counter()
+        losses = proc.train_surrogate(train, epochs=args.epochs, batch=16384, lr=2e-3, lr_decay=0.7, seed=3003)
+        torch.cuda.synchronize()
+        return losses, time.perf_counter() - t0
+
+    def calls(sout, n_calls, bound=0.01):
+        proc.reweight_surrogate(mom, out=sout, audit_fraction=args.audit, seed=7, max_audit_error=1.0)
+        torch.cuda.synchronize()
+        times, stats, fb = [], None, False
+        for i in range(n_calls):
+            t0 = time.perf_counter()
+            _, stats, fb = proc.reweight_surrogate(mom, out=sout, audit_fraction=args.audit, seed=7 + i,
+                                                   max_audit_error=bound)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        err = torch.abs(sout / exact_out - 1.0)
+        return 1e3 * float(np.mean(times)), err, stats, fb
+
+    losses, t_train = fit()
+    log(f"surrogate: trained in {t_train:.2f}s, losses {losses}")
+    sout = torch.empty_like(exact_out)
+    ms, err, stats, fb = calls(sout, args.steps)
     e_mean = float(err.mean())
     e_p99 = float(torch.quantile(err.flatten()[:: max(1, err.numel() // 4000000)].float(), 0.99))
-    return {"value": args.n * args.points / (ms * 1e-3), "unit": "events*points/s", "ms_per_step": ms,
-            "mean_abs_weight_err": e_mean, "p99_abs_weight_err": e_p99, "audit_fraction": args.audit,
-            "audit_mean_err_estimate": float(np.mean(stats[:, 2])), "fell_back": bool(fb),
-            "train_events": args.train_events, "epochs": args.epochs, "train_seconds": t_train,
-            "final_loss": float(losses[-1]),
-            "timing": "host wall clock per call (the call synchronises once for the audit statistics)"}
+    work = args.n * args.points
+    res = {"value": work / (ms * 1e-3), "unit": "events*points/s", "ms_per_step": ms,
+           "mean_abs_weight_err": e_mean, "p99_abs_weight_err": e_p99, "audit_fraction": args.audit,
+           "audit_mean_err_estimate": float(np.mean(stats[:, 2])), "fell_back": bool(fb),
+           "train_events": args.train_events, "epochs": args.epochs, "train_seconds": t_train,
+           "final_loss": float(losses[-1]), "inputs": 53,
+           "timing": "host wall clock per call (the call synchronises once for the audit statistics)",
+           "amortised": {
+               "value_one_batch_with_training": work / (t_train + ms * 1e-3),
+               "break_even_batches_vs_exact": t_train / ((exact_ms - ms) * 1e-3),
+               "break_even_batches_vs_kpoly": (t_train / ((kpoly_ms - ms) * 1e-3)) if kpoly_ms else None,
+               "note": "training (exact labels included) + one audited call per batch of the same size; "
+                       "break-even = batches after which training plus calls cost less than the exact path"}}
+    # the workload's 25 inputs (momentum components and kappa), same training
+    proc.set_surrogate_inputs(25)
+    losses25, t25 = fit()
+    # no fallback: the network's own error (an audit bound of 1 % would fall
+    # back to the exact path where it exceeds that)
+    ms25, err25, st25, _ = calls(sout, 1, bound=1.0)
+    proc.set_surrogate_inputs(53)
+    log(f"surrogate (25 inputs): trained in {t25:.2f}s, mean err {float(err25.mean()):.4f}")
+    res["inputs_25"] = {"mean_abs_weight_err": float(err25.mean()), "final_loss": float(losses25[-1]),
+                        "audit_mean_err_estimate": float(np.mean(st25[:, 2])), "train_seconds": t25,
+                        "falls_back_at_1pct": bool((st25[:, 2] > 0.01).any())}
+    del train
+    return res
 
 
 def kpoly_leg(args, proc, mom, exact_out, stream, torch, n_eval):
@@ -406,7 +436,8 @@ def main():
         log("kappa-polynomial variant")
         res["kpoly"] = kpoly_leg(args, proc, mom, out, stream, torch, n_eval)
     if not args.no_surrogate and args.proc != "ee_5a":
-        res["surrogate"] = surrogate_leg(args, proc, mom, out, kap, torch, generate_events)
+        res["surrogate"] = surrogate_leg(args, proc, mom, out, kap, torch, generate_events, ms,
+                                         res.get("kpoly", {}).get("ms_per_step"))
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, args.n)
         log(f"cpu baseline: oracle on {sample} events")

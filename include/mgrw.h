@@ -199,6 +199,14 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
  * accumulation; results agree with the default VALU form to float32
  * rounding) after the last program part; default 0.
  *
+ * MGRW_OPT_SURROGATE_INPUTS (53 or 25): input features of the surrogate that
+ * mgrw_surrogate_train fits and mgrw_reweight_surrogate evaluates (events
+ * in, not mgrw_surrogate_train_samples): 53 (default) = the 24 momentum
+ * components over sqrt(s)/2, (kappa - 1)/0.2, and 2 p_i.p_j/s with its
+ * logarithm for the 14 pairs other than the beams; 25 = the momentum
+ * components and kappa only (the other columns zero).  A network must be
+ * evaluated with the setting it was trained with.
+ *
  * MGRW_OPT_KERNEL_TIMING (0 or 1): when 1, every launch records a pair of HIP
  * events on its stream around its amplitude kernel(s) (after the setup of
  * the kinematics, before the FP64 re-evaluation), read by
@@ -207,7 +215,8 @@ mgrw_status mgrw_process_info(const mgrw_process *p, int *n_ext, int *n_flows, i
  * Errors: MGRW_ERR_ARG (unknown option or value), MGRW_ERR_UNSUPPORTED
  * (mapping or rescue not available for the process or precision),
  * MGRW_ERR_DEVICE (event creation failed). */
-enum { MGRW_OPT_LANE_MAPPING = 1, MGRW_OPT_RESCUE_PPM = 2, MGRW_OPT_KERNEL_TIMING = 3, MGRW_OPT_COLOUR_MFMA = 4 };
+enum { MGRW_OPT_LANE_MAPPING = 1, MGRW_OPT_RESCUE_PPM = 2, MGRW_OPT_KERNEL_TIMING = 3, MGRW_OPT_COLOUR_MFMA = 4,
+       MGRW_OPT_SURROGATE_INPUTS = 5 };
 enum { MGRW_MAP_AUTO = 0, MGRW_MAP_EVENT_PER_LANE = 1, MGRW_MAP_EVENT_PER_WAVE = 2 };
 mgrw_status mgrw_set_option(mgrw_process *p, int option, int64_t value);
 
@@ -310,8 +319,10 @@ typedef struct {
 
 /* Train the surrogate on n_events events (device momenta as for
  * mgrw_reweight) at the handle's current points: the exact kernels label every
- * (event, point) pair, then the network is fitted by mean-squared error with
- * Adam, all on the device.  A previous network is replaced, starting from a
+ * (event, point) pair (the kappa-polynomial evaluation of
+ * mgrw_reweight_kpoly where the process has it, exact up to rounding), then
+ * the network is fitted by mean-squared error with Adam on shuffled batches
+ * (a keyed permutation of the samples per epoch), all on the device.  A previous network is replaced, starting from a
  * seeded initialisation.  loss_out (host, may be NULL) receives the mean
  * training loss of each epoch.  Synchronous.  Errors: MGRW_ERR_ARG,
  * MGRW_ERR_UNSUPPORTED (e+e- process, or points that change more than

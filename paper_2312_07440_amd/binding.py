@@ -225,6 +225,11 @@ class Process:
         (mixed precision; 0 switches it off).  Stored in units of 1e-6."""
         check(lib().mgrw_set_option(self._h, 2, int(round(tau * 1e6))))
 
+    def set_surrogate_inputs(self, n):
+        """Surrogate input features for training on events and inference:
+        53 (momenta, kappa, pair invariants) or 25 (momenta and kappa)."""
+        check(lib().mgrw_set_option(self._h, 5, int(n)))
+
     @property
     def rescue_threshold(self):
         """The FP64 re-evaluation threshold tau in force (0: off)."""

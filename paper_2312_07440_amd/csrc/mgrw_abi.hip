@@ -294,6 +294,7 @@ mgrw_status mgrw_create_process(int proc, int prec, const mgrw_params* base, mgr
     p->timed = 0;
     p->colour_mfma = 0;
     p->hp = nullptr;
+    p->sur_inputs = MGRW_SURROGATE_N_FEATURES;
     *out = p;
     return MGRW_OK;
 }
@@ -372,6 +373,12 @@ mgrw_status mgrw_set_option(mgrw_process* p, int option, int64_t value) {
         p->colour_mfma = int(value);
         return MGRW_OK;
     }
+    if (option == MGRW_OPT_SURROGATE_INPUTS) {
+        if (value != MGRW_SURROGATE_N_FEATURES && value != 25)
+            return fail(MGRW_ERR_ARG, "surrogate inputs: 53 (with the pair invariants) or 25");
+        p->sur_inputs = int(value);
+        return MGRW_OK;
+    }
     if (option == MGRW_OPT_KERNEL_TIMING) {
         if (value != 0 && value != 1) return fail(MGRW_ERR_ARG, "kernel timing: 0 or 1");
         if (value == 1 && !p->t0) {
@@ -406,6 +413,7 @@ mgrw_status mgrw_get_option(const mgrw_process* p, int option, int64_t* value) {
         case MGRW_OPT_RESCUE_PPM: *value = int64_t(p->rescue_tau * 1e6 + 0.5); return MGRW_OK;
         case MGRW_OPT_KERNEL_TIMING: *value = p->t0 != nullptr; return MGRW_OK;
         case MGRW_OPT_COLOUR_MFMA: *value = p->colour_mfma; return MGRW_OK;
+        case MGRW_OPT_SURROGATE_INPUTS: *value = p->sur_inputs; return MGRW_OK;
         default: return fail(MGRW_ERR_ARG, "unknown option");
     }
 }

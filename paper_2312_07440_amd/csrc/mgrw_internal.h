@@ -31,4 +31,5 @@ struct mgrw_process {
     int timed;                          // a launch has recorded t0/t1
     int colour_mfma;                    // g g -> t tbar g g g: colour sum on the matrix cores
     mgrw::host_pipeline* hp;            // null until mgrw_reweight_host is first called
+    int sur_inputs;                     // surrogate input features: 53 (with pair invariants) or 25
 };

@@ -79,82 +79,6 @@ __host__ __device__ inline double u01(uint64_t seed, uint64_t stream, uint64_t i
     return (double(h >> 11) + 0.5) * 0x1.0p-53;
 }
 
-// ------------------------------------------------------------------ GEMM
-//
-// C[m][n] = sum_k A(m, k) B(k, n), bfloat16 operands, float accumulation,
-// on v_mfma_f32_32x32x16_bf16.  A(m, k) = A[m*sam + k*sak], B(k, n) =
-// B[k*sbk + n*sbn]; AKC (BKC): k is the contiguous index of A (B), else m (n)
-// is.  Tile 64 x 64 x 32 per 256-thread workgroup, each wave a 32 x 32 block;
-// grid (M/64, N/64, split-K slices).  M, N multiples of 64, K and the slice
-// multiples of 32.
-constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;
-
-enum { EPI_F32 = 0, EPI_FWD = 1, EPI_BWD = 2 };
-
-struct epi_args {
-    float* c;             // EPI_F32: C[slice][M][N]
-    const float* bias;    // EPI_FWD: bias[N]
-    float* zout;          // EPI_FWD: pre-activation (may be null)
-    uint16_t* aout;       // EPI_FWD: SiLU(z), bfloat16; EPI_BWD: dz, bfloat16
-    const float* zin;     // EPI_BWD: pre-activation of the layer below
-};
-
-template <bool AKC>
-__device__ __forceinline__ void load_tile(uint16_t (*S)[LDK], const uint16_t* __restrict__ G, int64_t s_mn,
-                                          int64_t s_k, int mn0, int k0, int t) {
-    if (AKC) {   // 64 rows x 32 k, k contiguous: 8 k per thread
-        int r = t >> 2, c = (t & 3) * 8;
-        uint4 v = *reinterpret_cast<const uint4*>(G + int64_t(mn0 + r) * s_mn + (k0 + c));
-        *reinterpret_cast<uint4*>(&S[r][c]) = v;
-    } else {     // 32 k x 64 rows, rows contiguous: 8 rows per thread, transposed into LDS
-        int kk = t >> 3, r = (t & 7) * 8;
-        uint4 v = *reinterpret_cast<const uint4*>(G + int64_t(k0 + kk) * s_k + (mn0 + r));
-        const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) S[r + j][kk] = e[j];
-    }
-}
-
-template <bool AKC, bool BKC, int EPI>
-__global__ void __launch_bounds__(256)
-gemm_bf16(const uint16_t* __restrict__ A, int64_t sam, int64_t sak, const uint16_t* __restrict__ B, int64_t sbk,
-          int64_t sbn, int M, int N, int K, int kslice, epi_args ep) {
-    __shared__ uint16_t As[BM][LDK];
-    __shared__ uint16_t Bs[BN][LDK];
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int kb = blockIdx.z * kslice, ke = min(K, kb + kslice);
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    f32x16 acc = {};
-    for (int k0 = kb; k0 < ke; k0 += BK) {
-        load_tile<AKC>(As, A, sam, sak, m0, k0, t);
-        load_tile<BKC>(Bs, B, sbn, sbk, n0, k0, t);
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 16) {
-            bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + (lane & 31)][kk + (lane >> 5) * 8]);
-            bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + (lane & 31)][kk + (lane >> 5) * 8]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-        }
-        __syncthreads();
-    }
-    const int col = n0 + wn + (lane & 31);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        const int64_t idx = int64_t(row) * N + col;
-        if (EPI == EPI_F32) {
-            ep.c[int64_t(blockIdx.z) * M * N + idx] = acc[r];
-        } else if (EPI == EPI_FWD) {
-            float z = acc[r] + ep.bias[col];
-            if (ep.zout) ep.zout[idx] = z;
-            ep.aout[idx] = f2bf(silu(z));
-        } else {
-            ep.aout[idx] = f2bf(acc[r] * dsilu(ep.zin[idx]));
-        }
-    }
-}
-
 // ------------------------------------------------------- elementwise kernels
 
 // Feature rows r = e*P + k of events [e0, e0 + rows/P): bfloat16 x[r][64],
@@ -166,8 +90,11 @@ struct kappa_set {
     double k[MGRW_MAX_POINTS];
 };
 
+// nin = 25 keeps only the momentum components and kappa (the invariants'
+// columns are zero).
 __global__ void features_kernel(const double* __restrict__ mom, int n_ext, int64_t n, int64_t e0, int P,
-                                kappa_set kappa, int64_t rows, uint16_t* __restrict__ x, float* __restrict__ kd) {
+                                kappa_set kappa, int64_t rows, int nin, uint16_t* __restrict__ x,
+                                float* __restrict__ kd) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= rows) return;
     const int64_t e = e0 + r / P;
@@ -190,30 +117,12 @@ __global__ void features_kernel(const double* __restrict__ mom, int n_ext, int64
                 v = float(u);
                 lv = float(log(fmax(u, 1e-12)));
             }
-            xr[c] = f2bf(v);
-            xr[c + 14] = f2bf(lv);
+            xr[c] = nin > c ? f2bf(v) : uint16_t(0);
+            xr[c + 14] = nin > c + 14 ? f2bf(lv) : uint16_t(0);
             ++c;
         }
     for (int i = NFEAT; i < K0; ++i) xr[i] = 0;
     kd[r] = float(kappa.k[k] - 1.0);
-}
-
-// Gather training samples s = perm[b0 + r]: event s / P, point s % P, from
-// features precomputed for all samples.
-__global__ void gather_kernel(const int32_t* __restrict__ perm, int64_t b0, int rows,
-                              const uint16_t* __restrict__ xall, const float* __restrict__ kdall,
-                              const float* __restrict__ yall, uint16_t* __restrict__ x, float* __restrict__ kd,
-                              float* __restrict__ y) {
-    const int t = threadIdx.x;
-    const int r = blockIdx.x;
-    if (r >= rows) return;
-    const int64_t s = perm[b0 + r];
-    if (t < K0 / 8)
-        reinterpret_cast<uint4*>(x + int64_t(r) * K0)[t] = reinterpret_cast<const uint4*>(xall + s * K0)[t];
-    if (t == 0) {
-        kd[r] = kdall[s];
-        y[r] = yall[s];
-    }
 }
 
 // Feature rows of given float features [m][NFEAT] (tests).
@@ -221,126 +130,6 @@ __global__ void features_from_f32(const float* __restrict__ xin, int64_t m, uint
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= m) return;
     for (int i = 0; i < K0; ++i) x[r * K0 + i] = i < NFEAT ? f2bf(xin[r * NFEAT + i]) : uint16_t(0);
-}
-
-// Output layer, 64 rows per block (4 threads per row): h = a4 . w5 + b5,
-// yhat = kd h.  Training: loss, dz4 = dh w5 silu'(z4) with dh = 2 (yhat - y)
-// kd / m_total, and block partials of dw5, db5.  Inference: w_out.
-template <bool TRAIN>
-__global__ void __launch_bounds__(256)
-head_kernel(const uint16_t* __restrict__ a4, const float* __restrict__ z4, const float* __restrict__ w5,
-            const float* __restrict__ b5, const float* __restrict__ kd, const float* __restrict__ y, int64_t m,
-            double inv_m_total, float* __restrict__ pred, uint16_t* __restrict__ dz4,
-            float* __restrict__ dw5_part, double* __restrict__ loss_acc,
-            // inference
-            int P, int64_t n_events, int64_t e0, const double* __restrict__ w_in, double* __restrict__ w_out) {
-    __shared__ float red[H + 1];
-    const int t = threadIdx.x, q = t & 3;
-    const int64_t row = int64_t(blockIdx.x) * 64 + (t >> 2);
-    if (TRAIN) {
-        for (int i = t; i <= H; i += 256) red[i] = 0.0f;
-        __syncthreads();
-    }
-    const bool ok = row < m;
-    float h = 0.0f;
-    if (ok) {
-        const uint16_t* ar = a4 + row * H + q * 64;
-        for (int j = 0; j < 64; ++j) h += bf2f(ar[j]) * w5[q * 64 + j];
-    }
-    h += __shfl_xor(h, 1);
-    h += __shfl_xor(h, 2);
-    h += b5[0];
-    const float kr = ok ? kd[row] : 0.0f;
-    const float yh = kr * h;
-    if (!TRAIN) {
-        if (ok && q == 0) {
-            const int64_t e = e0 + row / P;
-            const int k = int(row % P);
-            const double w = w_in ? w_in[e] : 1.0;
-            w_out[int64_t(k) * n_events + e] = w * exp(double(yh));
-            if (pred) pred[row] = yh;
-        }
-        return;
-    }
-    float dh = 0.0f;
-    if (ok) {
-        const float diff = yh - y[row];
-        dh = float(2.0 * double(diff) * inv_m_total) * kr;
-        if (q == 0) {
-            pred[row] = yh;
-            atomicAdd(loss_acc, double(diff) * double(diff) * inv_m_total);
-            atomicAdd(&red[H], dh);
-        }
-        const uint16_t* ar = a4 + row * H + q * 64;
-        const float* zr = z4 + row * H + q * 64;
-        uint16_t* dr = dz4 + row * H + q * 64;
-        for (int j = 0; j < 64; ++j) {
-            dr[j] = f2bf(dh * w5[q * 64 + j] * dsilu(zr[j]));
-            atomicAdd(&red[q * 64 + j], dh * bf2f(ar[j]));
-        }
-    }
-    __syncthreads();
-    for (int i = t; i <= H; i += 256) dw5_part[int64_t(blockIdx.x) * (H + 1) + i] = red[i];
-}
-
-// out[i] = sum over s of part[s][i]  (split-K and block partials)
-__global__ void reduce_parts(const float* __restrict__ part, int nparts, int64_t len, float* __restrict__ out) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= len) return;
-    float s = 0.0f;
-    for (int p = 0; p < nparts; ++p) s += part[int64_t(p) * len + i];
-    out[i] = s;
-}
-
-// out[i] = sum over s of part[s][i] for many partials of a short row (bias
-// and output-layer gradients): one workgroup per column i, its 256 threads
-// taking partials s = t, t + 256, ..., then a fixed-order tree; deterministic.
-__global__ void __launch_bounds__(256)
-reduce_cols(const float* __restrict__ part, int nparts, int64_t len, float* __restrict__ out) {
-    const int t = threadIdx.x;
-    const int64_t i = blockIdx.x;
-    float s = 0.0f;
-    for (int p = t; p < nparts; p += 256) s += part[int64_t(p) * len + i];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    __shared__ float w[4];
-    if ((t & 63) == 0) w[t >> 6] = s;
-    __syncthreads();
-    if (t == 0) out[i] = (w[0] + w[1]) + (w[2] + w[3]);
-}
-
-// Row chunks of the bias-gradient column sums: enough workgroups to spread
-// over the 256 CUs, few enough for one pass of the final reduction.
-constexpr int kBiasChunks = 256;
-
-// Partial column sums of a bfloat16 [m][H] matrix (bias gradients): block b
-// sums rows [b*rows_per, (b+1)*rows_per) of every column; deterministic.
-__global__ void colsum_bf16(const uint16_t* __restrict__ g, int64_t m, int64_t rows_per, float* __restrict__ part) {
-    const int c = threadIdx.x;
-    const int64_t r0 = int64_t(blockIdx.x) * rows_per, r1 = min(m, r0 + rows_per);
-    float s = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) s += bf2f(g[r * H + c]);
-    part[int64_t(blockIdx.x) * H + c] = s;
-}
-
-// Adam on the float32 master parameters; refresh the bfloat16 copy.
-__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
-                            float* __restrict__ m2, uint16_t* __restrict__ pbf, int64_t n, float lr, float b1,
-                            float b2, float eps, float c1, float c2) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
-    const float a = b1 * m1[i] + (1.0f - b1) * gi;
-    const float b = b2 * m2[i] + (1.0f - b2) * gi * gi;
-    m1[i] = a;
-    m2[i] = b;
-    const float v = p[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
-    p[i] = v;
-    pbf[i] = f2bf(v);
-}
-
-__global__ void to_bf16(const float* __restrict__ p, int64_t n, uint16_t* __restrict__ out) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = f2bf(p[i]);
 }
 
 // y = log(w) of the exact reweight output [P][n] into sample order s = e*P + k.
@@ -430,7 +219,7 @@ __global__ void audit_kernel(const int64_t* __restrict__ idx, int64_t na, const 
 // accumulator rows are four consecutive units of one feature row, stored as
 // one 8-byte word.  Rows are event-major (r = e P + k): layer 1 reads the
 // event's features (computed once per event) and the point's kappa.  Same
-// arithmetic as the layer-by-layer training kernels.  rows < 2^31.
+// arithmetic as the training kernels' forward pass.  rows < 2^31.
 constexpr int FR = 128;         // rows per workgroup
 constexpr int LDA = H + 8;      // LDS row stride (bfloat16)
 
@@ -574,6 +363,606 @@ audit_fill_kernel(uint64_t seed, double f, int64_t n, const int64_t* __restrict_
     }
 }
 
+// ------------------------------------------------------------- training
+//
+// One Adam step on a batch of B sample rows runs in six kernels:
+//   train_fwd_kernel  TR rows per workgroup through the four hidden layers
+//                     (activations in LDS, as in inference) and the output
+//                     unit: loss, dh = d loss / d h, the output layer's
+//                     gradient partials and dz4; it stores what the backward
+//                     pass needs (a_0..a_3, z_1..z_3, dz4);
+//   train_bwd_kernel  per hidden layer l = 4, 3, 2, 1, two kinds of workgroup
+//                     in one launch: TR-row tiles of dz_{l-1} = (dz_l W_l) *
+//                     SiLU'(z_{l-1}) (l > 1), and
+//                     64 x 64 tiles of dW_l = dz_l^T a_{l-1} over one of
+//                     kSlices slices of the rows (split-K partials; the tiles
+//                     of the first k columns also sum dz_l over the slice:
+//                     the bias gradient's partials);
+//   adam_kernel       sums the partials, updates the float32 parameters and
+//                     refreshes both bfloat16 copies of the weights (row-major
+//                     for the forward pass, transposed for dz_l W_l); the
+//                     output layer's parameters and the loss, with partials
+//                     per row tile, take one wave each.
+// Rounding points: features, weights, activations a_l and back-propagated
+// dz_l in bfloat16, pre-activations z_l and all accumulation in float32.
+// Pre-activations z_l stay float32 and are stored in the order in which the
+// lanes of the forward epilogue hold them and the lanes of the dz epilogue
+// need them (z_index), so each wave instruction moves 1 KB contiguously.
+// The bfloat16 matrices a_l and dz_l live in an 8-row blocked layout: element
+// (m, c) of a [rows][C] matrix at ((m / 8) C + c) 8 + m % 8.  Eight
+// consecutive rows of one column are then 16 contiguous bytes, which is one
+// matrix-core operand register of the weight-gradient product (the reduction
+// runs over rows): its operands come straight from L2, without LDS staging.
+// Sample order: a keyed bijection of [0, samples) per epoch (a four-round
+// Feistel network on the next even power of two, cycle-walking into range).
+
+constexpr int kSlices = 16;   // split-K slices of the weight gradients
+constexpr int kFwdWaves = 8;  // waves per forward workgroup
+constexpr int kRowAlign = 1024;   // batch buffers are padded to this many rows (4 waves x kSlices x 16)
+
+// offset of layer l's (1..4) weight-gradient partials [kSlices][H][K_l]
+__host__ __device__ constexpr int64_t pw_off(int layer) {
+    return layer <= 1 ? 0 : int64_t(kSlices) * (int64_t(H) * K0 + int64_t(layer - 2) * H * H);
+}
+constexpr int64_t kPwFloats = pw_off(5);
+
+struct train_bufs {
+    uint16_t* xb;      // a_0 (features), blocked [rows/8][K0][8]
+    uint16_t* ab[3];   // a_1..a_3, blocked [rows/8][H][8]
+    float* z[3];       // z_1..z_3 in the matrix-core lane order (z_index)
+    uint16_t* dzb[2];  // dz_l ping-pong, blocked [rows/8][H][8]: dz4, dz2 in [0]; dz3, dz1 in [1]
+    float* pw;         // weight-gradient partials, kPwFloats
+    float* pb;         // bias-gradient partials [layer 0..3][kSlices][H]
+    float* pw5;        // output-layer partials [row tile][H + 1] (w5, then b5)
+    double* ploss;     // loss partials [row tile]
+    float* pred;       // predictions [rows]
+};
+
+// Where the rows of a batch come from.  P > 1: x holds one feature row per
+// event and sample s is event s / P at point s % P (kappa column and kd from
+// the point's kappa); P == 1: x and kd hold one row per sample.
+struct train_src {
+    const uint16_t* x;
+    const float* kd;
+    const float* y;
+    int P;
+    kappa_set kappa;
+    int64_t ns;        // samples
+    uint64_t key;      // permutation key of the epoch
+    int shuffle;       // 0: sample i is row i of the sweep
+    int hb;            // half width (bits) of the permutation domain, 4^hb >= ns
+};
+
+// Offset (in float4) of the four pre-activations a lane holds after a
+// layer's product D = W A^T: row tile gt (rows 32 gt ..), unit block ub
+// (units 32 ub ..), accumulator group g, lane: units 32 ub + 8 g + 4 (lane /
+// 32) .. + 3 of row 32 gt + lane % 32.
+__device__ __forceinline__ int64_t z_index(int64_t gt, int ub, int g, int lane) {
+    return ((gt * 8 + ub) * 4 + g) * 64 + lane;
+}
+
+// The sample at position i of the epoch's order.
+__host__ __device__ inline int64_t sample_at(const train_src& S, int64_t i) {
+    if (!S.shuffle) return i;
+    const uint64_t mask = (uint64_t(1) << S.hb) - 1;
+    uint64_t x = uint64_t(i);
+    do {
+        uint64_t L = x >> S.hb, R = x & mask;
+        for (int r = 0; r < 4; ++r) {
+            const uint64_t F = smix(S.key + 0x9E3779B97F4A7C15ull * uint64_t(r + 1) + R) & mask;
+            const uint64_t T = L ^ F;
+            L = R;
+            R = T;
+        }
+        x = (L << S.hb) | R;
+    } while (x >= uint64_t(S.ns));
+    return int64_t(x);
+}
+
+// LDS of the backward kernel: TR = 32 RT rows of dz, or (weight gradient)
+// two waves' 64 x 64 float tiles for the reduction over the four waves.
+template <int RT>
+struct rows_lds {
+    union {
+        uint16_t act[32 * RT][LDA];
+        float red[2 * 64 * 64];
+    };
+};
+
+// LDS rows [0, TR) x C columns -> blocked layout at global rows r0.. .
+template <int TR, int C, int NT = 256>
+__device__ __forceinline__ void store_blocked(const uint16_t (*act)[LDA], uint16_t* __restrict__ dst, int r0, int t) {
+    constexpr int NB = TR / 8;   // 8-row blocks
+    static_assert(C == H || C == K0, "feature or hidden width");
+    constexpr int TPC = NT / C;   // threads per column
+    const int c = t % C;
+    for (int b = t / C; b < NB; b += TPC) {
+        uint32_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            w[j] = uint32_t(act[b * 8 + 2 * j][c]) | (uint32_t(act[b * 8 + 2 * j + 1][c]) << 16);
+        *reinterpret_cast<uint4*>(dst + (int64_t(r0 / 8 + b) * C + c) * 8) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// Blocked layout at global rows r0.. -> LDS rows [0, TR) x C columns.
+template <int TR, int C, int NT = 256>
+__device__ __forceinline__ void load_blocked(const uint16_t* __restrict__ src, uint16_t (*act)[LDA], int r0, int t) {
+    constexpr int NB = TR / 8;
+    constexpr int TPC = NT / C, NPT = (NB + TPC - 1) / TPC;   // threads per column, blocks per thread
+    const int c = t % C, b0 = t / C;
+    uint4 v[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i)   // every load first, then the LDS writes
+        if (b0 + i * TPC < NB) v[i] = *reinterpret_cast<const uint4*>(src + (int64_t(r0 / 8 + b0 + i * TPC) * C + c) * 8);
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int b = b0 + i * TPC;
+        if (b >= NB) break;
+        const uint32_t w[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            act[b * 8 + 2 * j][c] = uint16_t(w[j] & 0xffffu);
+            act[b * 8 + 2 * j + 1][c] = uint16_t(w[j] >> 16);
+        }
+    }
+}
+
+// Forward pass, loss and output-layer backward of TR = 32 RT rows per
+// workgroup (rows b0 + r of the epoch's order) with NW waves, each owning
+// UT = 8 / NW tiles of 32 units of every layer; see the section comment.
+template <int RT, int NW>
+__global__ void __launch_bounds__(64 * NW, 4)
+train_fwd_kernel(train_src S, int64_t b0, int rows, double inv_m, const uint16_t* __restrict__ wbf,
+                 const float* __restrict__ par, train_bufs T) {
+    constexpr int TR = 32 * RT, UT = 8 / NW, NT = 64 * NW;
+    __shared__ __align__(16) uint16_t act[TR][LDA];
+    __shared__ float kd_s[TR], y_s[TR], dh_s[TR];
+    __shared__ double lred[NW];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, lr = lane & 31, lh = lane >> 5;
+    const int r0 = int(blockIdx.x) * TR;
+    // the weight operands of a whole layer (UT x 16 k-steps of 16 bytes per
+    // lane): layer 0's requested first, each next layer's right after the last
+    // product of the current one, so that a layer waits for its weights once
+    constexpr int KSMAX = H / 16;
+    bf16x8 wq[UT][KSMAX];
+    auto wload = [&](int l) {
+        const int K = K_IN[l];
+        const uint16_t* W = wbf + W_OFF[l];   // [H][K]
+#pragma unroll
+        for (int ut = 0; ut < UT; ++ut)
+#pragma unroll
+            for (int ks = 0; ks < KSMAX; ++ks)
+                if (ks < K / 16)
+                    wq[ut][ks] = *reinterpret_cast<const bf16x8*>(W + ((wave * UT + ut) * 32 + lr) * K + ks * 16 + lh * 8);
+    };
+    wload(0);
+    // every load of the prologue is issued before any of them is waited
+    // for: biases and output layer (to LDS), the rows' features, kd and y
+    __shared__ __align__(16) float pls[4 * H + H + 1];
+    constexpr int NPL = (4 * H + H + 1 + NT - 1) / NT;
+    float pv[NPL];
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) {
+        const int i = t + j * NT;   // b1..b4 (B_OFF[l] = OFF_B1 + l (H H + H)), then w5, b5
+        if (i < 4 * H + H + 1)
+            pv[j] = par[i < 4 * H ? OFF_B1 + (i / H) * (int64_t(H) * H + H) + i % H : OFF_W5 + (i - 4 * H)];
+    }
+    // rows: TR rows, 256 / TR of the first 256 threads per row
+    constexpr int TPR = 256 / TR, CPT = K0 / TPR;   // threads per row, feature columns per thread
+    const int mrow = t / TPR, q = t % TPR, r = r0 + mrow;
+    const bool live = t < 256 && r < rows;
+    const bool owner = t < 256 && q == (NRAW - 1) / CPT;   // the thread that copies column 24 of the row
+    const int64_t smp = live ? sample_at(S, b0 + r) : 0;
+    const uint32_t ev = S.P > 1 ? uint32_t(smp) / uint32_t(S.P) : uint32_t(smp);   // samples < 2^31
+    const int pk = S.P > 1 ? int(uint32_t(smp) - ev * uint32_t(S.P)) : 0;
+    uint4 xv[CPT / 8];
+#pragma unroll
+    for (int i = 0; i < CPT / 8; ++i)
+        xv[i] = live ? reinterpret_cast<const uint4*>(S.x + int64_t(ev) * K0 + q * CPT)[i] : make_uint4(0u, 0u, 0u, 0u);
+    float kd = 0.0f, y = 0.0f;
+    if (live && owner) {
+        kd = S.P > 1 ? float(S.kappa.k[pk] - 1.0) : S.kd[smp];
+        y = S.y[smp];
+    }
+#pragma unroll
+    for (int j = 0; j < NPL; ++j)
+        if (t + j * NT < 4 * H + H + 1) pls[t + j * NT] = pv[j];
+    if (t < 256) {
+#pragma unroll
+        for (int i = 0; i < CPT / 8; ++i) reinterpret_cast<uint4*>(&act[mrow][q * CPT])[i] = xv[i];
+        if (owner) {
+            if (live && S.P > 1) act[mrow][NRAW - 1] = f2bf(float((S.kappa.k[pk] - 1.0) / 0.2));
+            kd_s[mrow] = kd;
+            y_s[mrow] = y;
+        }
+    }
+    __syncthreads();
+    store_blocked<TR, K0, NT>(act, T.xb, r0, t);
+    f32x16 acc[UT][RT];   // [unit tile][row tile]; after layer 4: z4
+    // the layers unrolled: constant trip counts and offsets let every wait
+    // count only the loads it needs
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const int KS = K_IN[l] / 16;
+#pragma unroll
+        for (int ut = 0; ut < UT; ++ut)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) acc[ut][rt] = f32x16{};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            bf16x8 x[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                x[rt] = *reinterpret_cast<const bf16x8*>(&act[rt * 32 + lr][ks * 16 + lh * 8]);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ut = 0; ut < UT; ++ut)
+                    acc[ut][rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq[ut][ks], x[rt], acc[ut][rt], 0, 0, 0);
+        }
+        if (l < 3) wload(l + 1);
+        __syncthreads();   // every wave has read the layer's input
+#pragma unroll
+        for (int ut = 0; ut < UT; ++ut)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int ub = wave * UT + ut;          // unit block
+                const int n = ub * 32 + g * 8 + lh * 4;   // units n .. n+3
+                const float4 bn = *reinterpret_cast<const float4*>(&pls[l * H + n]);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    f32x16& c = acc[ut][rt];
+                    const float4 z = make_float4(c[4 * g] + bn.x, c[4 * g + 1] + bn.y, c[4 * g + 2] + bn.z,
+                                                 c[4 * g + 3] + bn.w);
+                    if (l < 3) {
+                        reinterpret_cast<float4*>(T.z[l])[z_index(r0 / 32 + rt, ub, g, lane)] = z;
+                    } else {   // z4 stays for dz4
+                        c[4 * g] = z.x;
+                        c[4 * g + 1] = z.y;
+                        c[4 * g + 2] = z.z;
+                        c[4 * g + 3] = z.w;
+                    }
+                    *reinterpret_cast<uint2*>(&act[rt * 32 + lr][n]) =
+                        make_uint2(pack_bf16(silu(z.x), silu(z.y)), pack_bf16(silu(z.z), silu(z.w)));
+                }
+            }
+        __syncthreads();
+        if (l < 3) store_blocked<TR, H, NT>(act, T.ab[l], r0, t);
+    }
+    // output unit, loss and dh; HPR of the first 256 threads per row
+    constexpr int HPR = 256 / TR, UPT = H / HPR;   // threads per row, hidden units per thread
+    double lo = 0.0;
+    if (t < 256) {
+        const int mrow = t / HPR, q = t % HPR, r = r0 + mrow;
+        const bool live = r < rows;
+        float h = 0.0f;
+        const uint4* ar = reinterpret_cast<const uint4*>(&act[mrow][q * UPT]);
+        const float4* w5h = reinterpret_cast<const float4*>(&pls[4 * H + q * UPT]);
+#pragma unroll
+        for (int j = 0; j < UPT / 8; ++j) {
+            const uint4 a8 = ar[j];
+            const float4 wa = w5h[2 * j], wb = w5h[2 * j + 1];
+            h += __uint_as_float(a8.x << 16) * wa.x + __uint_as_float(a8.x & 0xffff0000u) * wa.y;
+            h += __uint_as_float(a8.y << 16) * wa.z + __uint_as_float(a8.y & 0xffff0000u) * wa.w;
+            h += __uint_as_float(a8.z << 16) * wb.x + __uint_as_float(a8.z & 0xffff0000u) * wb.y;
+            h += __uint_as_float(a8.w << 16) * wb.z + __uint_as_float(a8.w & 0xffff0000u) * wb.w;
+        }
+#pragma unroll
+        for (int o = 1; o < HPR; o <<= 1) h += __shfl_xor(h, o);
+        h += pls[5 * H];
+        const float kr = kd_s[mrow];
+        const float yh = kr * h;
+        const float diff = yh - y_s[mrow];
+        if (q == 0) {
+            const float dh = live ? float(2.0 * double(diff) * inv_m) * kr : 0.0f;
+            dh_s[mrow] = dh;
+            if (live) {
+                T.pred[r] = yh;
+                lo = double(diff) * double(diff) * inv_m;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lo += __shfl_xor(lo, o, 64);
+    if (lane == 0) lred[wave] = lo;
+    __syncthreads();
+    if (t < 256) {
+        // output-layer gradient partials of the tile: dw5[n] = sum dh a4[n], db5 = sum dh
+        float sw = 0.0f;
+        for (int m = 0; m < TR; ++m) sw += dh_s[m] * bf2f(act[m][t]);
+        T.pw5[int64_t(blockIdx.x) * (H + 1) + t] = sw;
+        if (t == 0) {
+            float sb = 0.0f;
+            for (int m = 0; m < TR; ++m) sb += dh_s[m];
+            T.pw5[int64_t(blockIdx.x) * (H + 1) + H] = sb;
+            double sl = 0.0;
+            for (int w = 0; w < NW; ++w) sl += lred[w];
+            T.ploss[blockIdx.x] = sl;
+        }
+    }
+    __syncthreads();   // a4 is read; dz4 replaces it
+#pragma unroll
+    for (int ut = 0; ut < UT; ++ut)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int n = (wave * UT + ut) * 32 + g * 8 + lh * 4;
+            const float4 w5 = *reinterpret_cast<const float4*>(&pls[4 * H + n]);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const f32x16& c = acc[ut][rt];
+                const float dh = dh_s[rt * 32 + lr];
+                *reinterpret_cast<uint2*>(&act[rt * 32 + lr][n]) =
+                    make_uint2(pack_bf16(dh * w5.x * dsilu(c[4 * g]), dh * w5.y * dsilu(c[4 * g + 1])),
+                               pack_bf16(dh * w5.z * dsilu(c[4 * g + 2]), dh * w5.w * dsilu(c[4 * g + 3])));
+            }
+        }
+    __syncthreads();
+    store_blocked<TR, H, NT>(act, T.dzb[0], r0, t);
+}
+
+// Backward through hidden layer `layer` (1..4): blocks [0, n_da) form
+// dz_{layer-1} for TR-row tiles (layer > 1), the others the weight-gradient
+// partials of one 64 x 64 tile and one slice of the rows.  rows_pad: the
+// batch rounded up to kRowAlign (each of the slice's four waves takes
+// rows_pad / (4 kSlices) rows).
+template <int RT, int KIN, bool DA>
+__global__ void __launch_bounds__(256, 2)
+train_bwd_kernel(int layer, int rows, int rows_pad, int n_da, const uint16_t* __restrict__ wt, train_bufs T) {
+    constexpr int TR = 32 * RT;
+    __shared__ __align__(16) rows_lds<RT> L;
+    uint16_t (*act)[LDA] = L.act;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, lr = lane & 31, lh = lane >> 5;
+    const uint16_t* __restrict__ dz = T.dzb[(4 - layer) & 1];
+    if constexpr (DA) {
+        if (int(blockIdx.x) < n_da) {
+            const int r0 = int(blockIdx.x) * TR;
+            // the pre-activations z_{layer-1} of this lane's (unit, row)
+            // pairs, requested first: they arrive while the product runs
+            const float4* __restrict__ zb = reinterpret_cast<const float4*>(T.z[layer - 2]);
+            float4 zv[2][4][RT];
+#pragma unroll
+            for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt) zv[ut][g][rt] = zb[z_index(r0 / 32 + rt, wave * 2 + ut, g, lane)];
+            load_blocked<TR, H>(dz, act, r0, t);   // dz_layer rows r0.. into row-major LDS
+            __syncthreads();
+            // D[k][m] = sum_n W[n][k] dz[m][n]: the transposed weights (row k
+            // contiguous in n) as the first operand, dz rows as the second
+            f32x16 acc[2][RT];
+#pragma unroll
+            for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) acc[ut][rt] = f32x16{};
+#pragma unroll 2
+            for (int ks = 0; ks < H / 16; ++ks) {
+                bf16x8 w[2], x[RT];
+#pragma unroll
+                for (int ut = 0; ut < 2; ++ut)
+                    w[ut] = *reinterpret_cast<const bf16x8*>(wt + ((wave * 2 + ut) * 32 + lr) * H + ks * 16 + lh * 8);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    x[rt] = *reinterpret_cast<const bf16x8*>(&act[rt * 32 + lr][ks * 16 + lh * 8]);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int ut = 0; ut < 2; ++ut)
+                        acc[ut][rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[ut], x[rt], acc[ut][rt], 0, 0, 0);
+            }
+            __syncthreads();   // every wave has read dz_layer
+#pragma unroll
+            for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int k = (wave * 2 + ut) * 32 + g * 8 + lh * 4;   // units k .. k+3 of layer-1
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt) {
+                        const f32x16& c = acc[ut][rt];
+                        const float4 z = zv[ut][g][rt];
+                        *reinterpret_cast<uint2*>(&act[rt * 32 + lr][k]) =
+                            make_uint2(pack_bf16(c[4 * g] * dsilu(z.x), c[4 * g + 1] * dsilu(z.y)),
+                                       pack_bf16(c[4 * g + 2] * dsilu(z.z), c[4 * g + 3] * dsilu(z.w)));
+                    }
+                }
+            __syncthreads();
+            store_blocked<TR, H>(act, T.dzb[1 - ((4 - layer) & 1)], r0, t);
+            return;
+        }
+    }
+    // weight gradient dW[n][k] = sum_m dz[m][n] a[m][k] of a 64 x 64 tile over
+    // one slice of the rows; the four waves take consecutive quarters of it
+    constexpr int KT = KIN / 64;
+    const int b = int(blockIdx.x) - (DA ? n_da : 0);
+    const int tile = b % (4 * KT), slice = b / (4 * KT);
+    const int n0 = (tile / KT) * 64, k0 = (tile % KT) * 64;
+    const int R = rows_pad / (4 * kSlices);   // rows per wave, a multiple of 16
+    const int m_begin = (slice * 4 + wave) * R;
+    // rows of the batch only (beyond it dz is zero or never written); the
+    // last 16-row step may cover dead rows of the last row tile (dz = 0)
+    const int m_end = min(m_begin + R, rows);
+    const uint16_t* __restrict__ a = layer == 1 ? T.xb : T.ab[layer - 2];
+    const bool bias = k0 == 0;   // these tiles also sum dz over the slice
+    f32x16 acc[2][2];
+    float cs[2] = {0.0f, 0.0f};   // column sums of dz, units n0 + ut 32 + lr, this lane's rows
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
+    // operands of 16-row steps, kPrefetch steps in flight
+    constexpr int kPrefetch = 2;
+    bf16x8 A[kPrefetch][2], B[kPrefetch][2];
+    auto load = [&](int st, int m) {
+        const int64_t mb = (m >> 3) + lh;   // this lane's 8-row block
+#pragma unroll
+        for (int ut = 0; ut < 2; ++ut)
+            A[st][ut] = *reinterpret_cast<const bf16x8*>(dz + (mb * H + n0 + ut * 32 + lr) * 8);
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+            B[st][kt] = *reinterpret_cast<const bf16x8*>(a + (mb * KIN + k0 + kt * 32 + lr) * 8);
+    };
+#pragma unroll
+    for (int st = 0; st < kPrefetch; ++st)
+        if (m_begin + 16 * st < m_end) load(st, m_begin + 16 * st);
+    for (int m = m_begin; m < m_end; m += 16 * kPrefetch) {
+#pragma unroll
+        for (int st = 0; st < kPrefetch; ++st) {
+            if (m + 16 * st >= m_end) break;
+#pragma unroll
+            for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt)
+                    acc[ut][kt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[st][ut], B[st][kt], acc[ut][kt], 0, 0, 0);
+            if (bias) {
+#pragma unroll
+                for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) cs[ut] += float(A[st][ut][j]);
+            }
+            const int mn = m + 16 * (st + kPrefetch);
+            if (mn < m_end) load(st, mn);
+        }
+    }
+    if (bias) {
+        __shared__ float bred[4][64];
+#pragma unroll
+        for (int ut = 0; ut < 2; ++ut) {
+            const float v = cs[ut] + __shfl_xor(cs[ut], 32);   // both 8-row halves
+            if (lh == 0) bred[wave][ut * 32 + lr] = v;
+        }
+        __syncthreads();
+        if (t < 64)
+            T.pb[(int64_t(layer - 1) * kSlices + slice) * H + n0 + t] =
+                (bred[0][t] + bred[1][t]) + (bred[2][t] + bred[3][t]);
+    }
+    // sum of the four waves' tiles: waves 2, 3 hand theirs to waves 0, 1
+    // through LDS, then wave 1 to wave 0, which writes the slice's partial
+    float* red = L.red;   // [2][64][64]
+    auto tile_pass = [&](int slot, bool add) {
+#pragma unroll
+        for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int nl = ut * 32 + (r / 4) * 8 + lh * 4 + r % 4, kl = kt * 32 + lr;
+                    float& x = red[(slot * 64 + nl) * 64 + kl];
+                    if (add)
+                        acc[ut][kt][r] += x;
+                    else
+                        x = acc[ut][kt][r];
+                }
+    };
+    if (wave >= 2) tile_pass(wave - 2, false);
+    __syncthreads();
+    if (wave < 2) tile_pass(wave, true);
+    __syncthreads();
+    if (wave == 1) tile_pass(0, false);
+    __syncthreads();
+    if (wave == 0) {
+        tile_pass(0, true);
+        float* out = T.pw + pw_off(layer) + (int64_t(slice) * H + n0) * KIN + k0;
+#pragma unroll
+        for (int ut = 0; ut < 2; ++ut)
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int nl = ut * 32 + (r / 4) * 8 + lh * 4 + r % 4, kl = kt * 32 + lr;
+                    out[int64_t(nl) * KIN + kl] = acc[ut][kt][r];
+                }
+    }
+}
+
+// Adam on one parameter with gradient g (float32 master, bfloat16 copy).
+__device__ __forceinline__ float adam_update(float* __restrict__ p, float* __restrict__ m1, float* __restrict__ m2,
+                                             uint16_t* __restrict__ pbf, int64_t i, float g, float lr, float b1,
+                                             float b2, float eps, float c1, float c2) {
+    const float a = b1 * m1[i] + (1.0f - b1) * g;
+    const float b = b2 * m2[i] + (1.0f - b2) * g * g;
+    m1[i] = a;
+    m2[i] = b;
+    const float v = p[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+    p[i] = v;
+    pbf[i] = f2bf(v);
+    return v;
+}
+
+// Sum the gradient partials of one step; mode 0: Adam on the float32
+// parameters, refreshing the row-major and transposed bfloat16 weights, and
+// the step's loss added to *loss; mode 1: the gradient into grad and the loss
+// into *loss, parameters untouched.  Blocks [0, n_hidden): one thread per
+// hidden-layer parameter (kSlices partials each); then one wave per
+// output-layer parameter (w5, b5) and one for the loss, whose partials come
+// one per row tile (`tiles` of them).
+__global__ void __launch_bounds__(256)
+adam_kernel(float* __restrict__ p, float* __restrict__ m1, float* __restrict__ m2, uint16_t* __restrict__ pbf,
+            uint16_t* __restrict__ pbft, train_bufs T, int tiles, int n_hidden, int mode, float lr, float b1,
+            float b2, float eps, float c1, float c2, float* __restrict__ grad, double* __restrict__ loss) {
+    if (int(blockIdx.x) >= n_hidden) {
+        const int wv = (int(blockIdx.x) - n_hidden) * 4 + int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+        if (wv <= H) {   // w5[wv] or (wv == H) b5
+            float g = 0.0f;
+            for (int q = lane; q < tiles; q += 64) g += T.pw5[int64_t(q) * (H + 1) + wv];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o, 64);
+            if (lane == 0) {
+                if (mode == 1)
+                    grad[OFF_W5 + wv] = g;
+                else
+                    adam_update(p, m1, m2, pbf, OFF_W5 + wv, g, lr, b1, b2, eps, c1, c2);
+            }
+        } else if (wv == H + 1) {
+            double sl = 0.0;
+            for (int q = lane; q < tiles; q += 64) sl += T.ploss[q];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) sl += __shfl_xor(sl, o, 64);
+            if (lane == 0) *loss = (mode == 0 ? *loss : 0.0) + sl;
+        }
+        return;
+    }
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= OFF_W5) return;
+    int l = 3;
+    while (i < W_OFF[l]) --l;
+    float g = 0.0f;
+    const bool weight = i < B_OFF[l];
+    const int64_t wj = i - W_OFF[l];   // index within W_l
+    if (weight) {
+        const int64_t len = int64_t(H) * K_IN[l];
+        const float* pw = T.pw + pw_off(l + 1) + wj;
+#pragma unroll
+        for (int sl = 0; sl < kSlices; ++sl) g += pw[sl * len];
+    } else {
+        const float* pb = T.pb + int64_t(l) * kSlices * H + (i - B_OFF[l]);
+#pragma unroll
+        for (int sl = 0; sl < kSlices; ++sl) g += pb[sl * H];
+    }
+    if (mode == 1) {
+        grad[i] = g;
+        return;
+    }
+    const float v = adam_update(p, m1, m2, pbf, i, g, lr, b1, b2, eps, c1, c2);
+    if (weight && l >= 1) {   // W_l[n][k] -> Wt_l[k][n] (layers 2..4)
+        const int64_t n = wj / H, k = wj % H;
+        pbft[int64_t(l - 1) * H * H + k * H + n] = f2bf(v);
+    }
+}
+
+// Both bfloat16 copies of freshly set parameters.
+__global__ void to_bf16(const float* __restrict__ p, uint16_t* __restrict__ pbf, uint16_t* __restrict__ pbft) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= NPAR) return;
+    const uint16_t vb = f2bf(p[i]);
+    pbf[i] = vb;
+    for (int l = 1; l < 4; ++l)
+        if (i >= W_OFF[l] && i < B_OFF[l]) {
+            const int64_t wj = i - W_OFF[l], n = wj / H, k = wj % H;
+            pbft[int64_t(l - 1) * H * H + k * H + n] = vb;
+        }
+}
+
 // --------------------------------------------------------------- host side
 
 template <typename T>
@@ -613,11 +1002,11 @@ struct sbuf {   // scratch of one call, allocated and freed in the order of its 
 
 struct surrogate {
     dbuf<float> par, grad, m1, m2;
-    dbuf<uint16_t> pbf;
-    // activations of one batch
-    dbuf<uint16_t> x0, act[4], dz[2];
-    dbuf<float> z[4], kd, y, pred, part;
-    dbuf<double> lossd;
+    dbuf<uint16_t> pbf, pbft;   // bfloat16 weights: row-major, and W2..W4 transposed
+    // one batch (see train_bufs)
+    dbuf<uint16_t> xb, ab[3], dzb[2];
+    dbuf<float> z[3], pw, pb, pw5, pred;
+    dbuf<double> ploss, lossd;
     int64_t rows_cap = 0;
     int step = 0;
 };
@@ -632,25 +1021,32 @@ namespace {
         if (e_ != hipSuccess) return set_error(MGRW_ERR_DEVICE, std::string(#x ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+// Rows of the batch buffers for a batch of `rows` (padded to kRowAlign).
+int64_t padded_rows(int64_t rows) { return (rows + kRowAlign - 1) / kRowAlign * kRowAlign; }
+
 hipError_t ensure_rows(surrogate* s, int64_t rows) {
-    if (rows <= s->rows_cap) return hipSuccess;
+    const int64_t rc = padded_rows(rows);
+    if (rc <= s->rows_cap) return hipSuccess;
+    const int64_t tiles = rc / 32;   // row tiles of the smallest size
     hipError_t e;
-    if ((e = s->x0.alloc(size_t(rows) * K0)) != hipSuccess) return e;
-    for (int l = 0; l < 4; ++l) {
-        if ((e = s->act[l].alloc(size_t(rows) * H)) != hipSuccess) return e;
-        if ((e = s->z[l].alloc(size_t(rows) * H)) != hipSuccess) return e;
+    auto zero = [&](auto& b, size_t count) {
+        if ((e = b.alloc(count)) != hipSuccess) return false;
+        if ((e = hipMemset(b.p, 0, count * sizeof(*b.p))) != hipSuccess) return false;
+        return true;
+    };
+    if (!zero(s->xb, size_t(rc) * K0)) return e;
+    for (int l = 0; l < 3; ++l) {
+        if (!zero(s->ab[l], size_t(rc) * H)) return e;
+        if (!zero(s->z[l], size_t(rc) * H)) return e;
     }
     for (int l = 0; l < 2; ++l)
-        if ((e = s->dz[l].alloc(size_t(rows) * H)) != hipSuccess) return e;
-    if ((e = s->kd.alloc(rows)) != hipSuccess) return e;
-    if ((e = s->y.alloc(rows)) != hipSuccess) return e;
-    if ((e = s->pred.alloc(rows)) != hipSuccess) return e;
-    // split-K partials (<= 16 slices of H x H), output-layer block partials,
-    // and bias-gradient partials (<= kBiasChunks row chunks)
-    if ((e = s->part.alloc(std::max<size_t>(size_t(16) * H * H, size_t(rows / 64 + 1) * (H + 1)) +
-                           size_t(kBiasChunks) * H)) != hipSuccess)
-        return e;
-    s->rows_cap = rows;
+        if (!zero(s->dzb[l], size_t(rc) * H)) return e;
+    if (!zero(s->pw, size_t(kPwFloats))) return e;
+    if (!zero(s->pb, size_t(4) * kSlices * H)) return e;
+    if (!zero(s->pw5, size_t(tiles) * (H + 1))) return e;
+    if (!zero(s->pred, size_t(rc))) return e;
+    if (!zero(s->ploss, size_t(tiles))) return e;
+    s->rows_cap = rc;
     return hipSuccess;
 }
 
@@ -665,11 +1061,14 @@ mgrw_status new_surrogate(mgrw_process* p) {
     HIPCHK(s->m1.alloc(NPAR));
     HIPCHK(s->m2.alloc(NPAR));
     HIPCHK(s->pbf.alloc(NPAR));
+    HIPCHK(s->pbft.alloc(size_t(3) * H * H));
     HIPCHK(s->lossd.alloc(1));
     return MGRW_OK;
 }
 
-void init_params(std::vector<float>& w, uint64_t seed) {
+// nin: input features in use (the fan-in of the first layer; the weights of
+// unused input columns are zero).
+void init_params(std::vector<float>& w, uint64_t seed, int nin = NFEAT) {
     w.assign(NPAR, 0.0f);
     int64_t i = 0;
     auto fill = [&](int64_t off, int rows, int cols, int used_cols, double scale) {
@@ -678,91 +1077,66 @@ void init_params(std::vector<float>& w, uint64_t seed) {
                 w[off + int64_t(r) * cols + c] =
                     c < used_cols ? float((2.0 * u01(seed, 3, uint64_t(i++)) - 1.0) * scale) : 0.0f;
     };
-    fill(OFF_W1, H, K0, NFEAT, std::sqrt(6.0 / NFEAT));
+    fill(OFF_W1, H, K0, nin, std::sqrt(6.0 / nin));
     fill(OFF_W2, H, H, H, std::sqrt(6.0 / H));
     fill(OFF_W3, H, H, H, std::sqrt(6.0 / H));
     fill(OFF_W4, H, H, H, std::sqrt(6.0 / H));
     fill(OFF_W5, 1, H, H, 0.1 / std::sqrt(double(H)));
 }
 
-template <bool AKC, bool BKC, int EPI>
-void gemm(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk, int64_t sbn, int M, int N,
-          int K, int splits, const epi_args& ep, hipStream_t s) {
-    dim3 grid(M / BM, N / BN, splits);
-    hipLaunchKernelGGL((gemm_bf16<AKC, BKC, EPI>), grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, M, N, K,
-                       K / splits, ep);
-}
-
-// Forward through the hidden layers for `rows` feature rows in s->x0.
-void forward(surrogate* s, int64_t rows, bool keep_z, hipStream_t st) {
-    const uint16_t* in = s->x0.p;
-    for (int l = 0; l < 4; ++l) {
-        epi_args ep{};
-        ep.bias = s->par.p + B_OFF[l];
-        ep.zout = keep_z ? s->z[l].p : nullptr;
-        ep.aout = s->act[l].p;
-        // Z[m][n] = sum_k X[m][k] W[n][k]: A = X (k contiguous), B(k, n) = W[n*K + k] (k contiguous)
-        gemm<true, true, EPI_FWD>(in, K_IN[l], 1, s->pbf.p + W_OFF[l], 1, K_IN[l], int(rows), H, K_IN[l], 1, ep,
-                                  st);
-        in = s->act[l].p;
+train_bufs bufs_of(surrogate* s) {
+    train_bufs T;
+    T.xb = s->xb.p;
+    for (int l = 0; l < 3; ++l) {
+        T.ab[l] = s->ab[l].p;
+        T.z[l] = s->z[l].p;
     }
+    T.dzb[0] = s->dzb[0].p;
+    T.dzb[1] = s->dzb[1].p;
+    T.pw = s->pw.p;
+    T.pb = s->pb.p;
+    T.pw5 = s->pw5.p;
+    T.ploss = s->ploss.p;
+    T.pred = s->pred.p;
+    return T;
 }
 
-// Backward for one batch whose dz4 is in s->dz[0]; gradients into s->grad.
-mgrw_status backward(surrogate* s, int64_t rows, hipStream_t st) {
-    int cur = 0;
-    int splits = 16;   // split-K slices: each a multiple of 32 rows
-    while (splits > 1 && rows % (int64_t(32) * splits) != 0) --splits;
-    const int nchunk = int(std::min<int64_t>(kBiasChunks, rows));
-    const int64_t rows_per = (rows + nchunk - 1) / nchunk;
-    float* bias_part = s->part.p + size_t(16) * H * H;
-    for (int l = 3; l >= 0; --l) {
-        const uint16_t* dzl = s->dz[cur].p;
-        const uint16_t* below = l > 0 ? s->act[l - 1].p : s->x0.p;
-        const int kin = K_IN[l];
-        // dW[n][k] = sum_m dz[m][n] a[m][k]: A(n, m) = dz[m*H + n] (n contiguous),
-        // B(m, k) = a[m*kin + k] (k = output column contiguous)
-        epi_args ep{};
-        ep.c = s->part.p;
-        gemm<false, false, EPI_F32>(dzl, 1, H, below, kin, 1, H, kin, int(rows), splits, ep, st);
-        hipLaunchKernelGGL(reduce_parts, dim3(unsigned((H * kin + 255) / 256)), dim3(256), 0, st, s->part.p, splits,
-                           int64_t(H) * kin, s->grad.p + W_OFF[l]);
-        hipLaunchKernelGGL(colsum_bf16, dim3(unsigned(nchunk)), dim3(H), 0, st, dzl, rows, rows_per, bias_part);
-        hipLaunchKernelGGL(reduce_cols, dim3(H), dim3(256), 0, st, bias_part, nchunk, int64_t(H),
-                           s->grad.p + B_OFF[l]);
-        if (l > 0) {
-            // da[m][k] = sum_n dz[m][n] W[n][k]: A = dz (n contiguous as k), B(n, k) = W[n*H + k]
-            // (k = output column contiguous); fused with silu'(z) of layer l-1
-            epi_args eb{};
-            eb.aout = s->dz[1 - cur].p;
-            eb.zin = s->z[l - 1].p;
-            gemm<true, false, EPI_BWD>(dzl, H, 1, s->pbf.p + W_OFF[l], H, 1, int(rows), H, H, 1, eb, st);
-            cur = 1 - cur;
-        }
-    }
-    HIPCHK(hipGetLastError());
-    return MGRW_OK;
+template <int RT>
+void launch_step(surrogate* s, const train_src& S, int64_t b0, int rows, hipStream_t st) {
+    constexpr int TR = 32 * RT;
+    const train_bufs T = bufs_of(s);
+    const int tiles = (rows + TR - 1) / TR;
+    const int rp = int(padded_rows(rows));
+    hipLaunchKernelGGL((train_fwd_kernel<RT, kFwdWaves>), dim3(unsigned(tiles)), dim3(64 * kFwdWaves), 0, st, S, b0,
+                       rows, 1.0 / double(rows), s->pbf.p, s->par.p, T);
+    for (int layer = 4; layer >= 2; --layer)
+        hipLaunchKernelGGL((train_bwd_kernel<RT, H, true>), dim3(unsigned(tiles + 16 * kSlices)), dim3(256), 0, st,
+                           layer, rows, rp, tiles, s->pbft.p + size_t(layer - 2) * H * H, T);
+    hipLaunchKernelGGL((train_bwd_kernel<RT, K0, false>), dim3(unsigned(4 * kSlices)), dim3(256), 0, st, 1, rows, rp,
+                       0, static_cast<const uint16_t*>(nullptr), T);
 }
 
-// Loss, output layer and its backward for one batch.
-mgrw_status head_train(surrogate* s, int64_t rows, double inv_m, hipStream_t st) {
-    const unsigned blocks = unsigned((rows + 63) / 64);
-    hipLaunchKernelGGL((head_kernel<true>), dim3(blocks), dim3(256), 0, st, s->act[3].p, s->z[3].p,
-                       s->par.p + OFF_W5, s->par.p + OFF_B5, s->kd.p, s->y.p, rows, inv_m, s->pred.p, s->dz[0].p,
-                       s->part.p, s->lossd.p, 0, int64_t(0), int64_t(0), nullptr, nullptr);
-    // dw5 and db5 from the block partials (w5 and b5 are contiguous)
-    hipLaunchKernelGGL(reduce_cols, dim3(H + 1), dim3(256), 0, st, s->part.p, int(blocks), int64_t(H + 1),
-                       s->grad.p + OFF_W5);
-    HIPCHK(hipGetLastError());
-    return MGRW_OK;
-}
+// Row tiles of 32 rows: the most workgroups for a batch (the row-tile
+// kernels' time is one workgroup's latency once they all run at once).
+constexpr int kRT = 1;
+int step_tiles(int rows) { return (rows + 32 * kRT - 1) / (32 * kRT); }
 
-void adam(surrogate* s, float lr, hipStream_t st) {
-    s->step += 1;
+// Forward, backward and (mode 0) Adam for the batch at positions b0 .. b0 +
+// rows - 1 of the epoch's order; mode 1 writes the gradient to s->grad and
+// the loss to s->lossd instead of updating.
+void train_step(surrogate* s, const train_src& S, int64_t b0, int rows, int mode, float lr, hipStream_t st) {
+    launch_step<kRT>(s, S, b0, rows, st);
     const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - std::pow(b1, float(s->step)), c2 = 1.0f - std::pow(b2, float(s->step));
-    hipLaunchKernelGGL(adam_kernel, dim3(unsigned((NPAR + 255) / 256)), dim3(256), 0, st, s->par.p, s->grad.p,
-                       s->m1.p, s->m2.p, s->pbf.p, NPAR, lr, b1, b2, 1e-8f, c1, c2);
+    float c1 = 1.0f, c2 = 1.0f;
+    if (mode == 0) {
+        s->step += 1;
+        c1 = 1.0f - std::pow(b1, float(s->step));
+        c2 = 1.0f - std::pow(b2, float(s->step));
+    }
+    const int n_hidden = int((OFF_W5 + 255) / 256), n_out = (H + 2 + 3) / 4;   // w5, b5, loss: one wave each
+    hipLaunchKernelGGL(adam_kernel, dim3(unsigned(n_hidden + n_out)), dim3(256), 0, st, s->par.p, s->m1.p, s->m2.p,
+                       s->pbf.p, s->pbft.p, bufs_of(s), step_tiles(rows), n_hidden, mode, lr, b1, b2, 1e-8f, c1, c2,
+                       s->grad.p, s->lossd.p);
 }
 
 mgrw_status check_qcd_kappa_only(const mgrw_process* p) {
@@ -796,50 +1170,35 @@ int64_t audit_size(uint64_t seed, double f, int64_t n) {
     return c;
 }
 
-// Fit a freshly initialised network (seeded) to ns samples: bfloat16
-// feature rows xall [ns][64], kd = kappa - 1, targets y; Adam on shuffled
-// batches, per-epoch mean loss into loss_out (host, may be NULL).
-mgrw_status train_core(mgrw_process* p, const uint16_t* xall, const float* kdall, const float* yall, int64_t ns,
-                       const mgrw_train_config* cfg, double* loss_out, hipStream_t st) {
+// Fit a freshly initialised network (seeded) to the samples of S (their
+// order shuffled per epoch by S's permutation); per-epoch mean loss into
+// loss_out (host, may be NULL).
+mgrw_status train_core(mgrw_process* p, train_src S, const mgrw_train_config* cfg, double* loss_out,
+                       hipStream_t st, int nin = NFEAT) {
     std::vector<float> w0;
-    init_params(w0, cfg->seed);
+    init_params(w0, cfg->seed, nin);
     mgrw_status r = mgrw_surrogate_set(p, w0.data());
     if (r != MGRW_OK) return r;
     surrogate* s = p->sur;
     const int64_t B = cfg->batch;
     HIPCHK(ensure_rows(s, B));
-    const int64_t nb = ns / B;
+    const int64_t nb = S.ns / B;
     if (nb < 1) return set_error(MGRW_ERR_ARG, "fewer samples than one batch");
-    std::vector<int32_t> perm(ns);
-    dbuf<int32_t> dperm;
-    HIPCHK(dperm.alloc(size_t(ns)));
+    S.shuffle = 1;
+    S.hb = 1;
+    while ((int64_t(1) << (2 * S.hb)) < S.ns) ++S.hb;
     float lr = float(cfg->lr);
     for (int ep = 0; ep < cfg->epochs; ++ep) {
-        for (int64_t i = 0; i < ns; ++i) perm[i] = int32_t(i);
-        for (int64_t i = ns - 1; i > 0; --i) {   // Fisher-Yates with a counter-based generator
-            int64_t j = int64_t(u01(cfg->seed + 7919 * uint64_t(ep + 1), 3, uint64_t(i)) * double(i + 1));
-            if (j > i) j = i;
-            std::swap(perm[i], perm[j]);
-        }
-        HIPCHK(hipMemcpyAsync(dperm.p, perm.data(), size_t(ns) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        S.key = smix(cfg->seed + 7919 * uint64_t(ep + 1));
         HIPCHK(hipMemsetAsync(s->lossd.p, 0, sizeof(double), st));
-        for (int64_t b = 0; b < nb; ++b) {
-            hipLaunchKernelGGL(gather_kernel, dim3(unsigned(B)), dim3(64), 0, st, dperm.p, b * B, int(B), xall,
-                               kdall, yall, s->x0.p, s->kd.p, s->y.p);
-            forward(s, B, true, st);
-            r = head_train(s, B, 1.0 / double(B), st);
-            if (r != MGRW_OK) return r;
-            r = backward(s, B, st);
-            if (r != MGRW_OK) return r;
-            adam(s, lr, st);
-        }
+        for (int64_t b = 0; b < nb; ++b) train_step(s, S, b * B, int(B), 0, lr, st);
+        HIPCHK(hipGetLastError());
         double lsum = 0.0;
         HIPCHK(hipMemcpyAsync(&lsum, s->lossd.p, sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (loss_out) loss_out[ep] = lsum / double(nb);
         lr *= float(cfg->lr_decay);
     }
-    HIPCHK(hipGetLastError());
     return MGRW_OK;
 }
 
@@ -859,7 +1218,7 @@ mgrw_status mgrw_surrogate_set(mgrw_process* p, const float* params) {
     HIPCHK(hipMemset(s->m1.p, 0, NPAR * sizeof(float)));
     HIPCHK(hipMemset(s->m2.p, 0, NPAR * sizeof(float)));
     s->step = 0;
-    hipLaunchKernelGGL(to_bf16, dim3(unsigned((NPAR + 255) / 256)), dim3(256), 0, 0, s->par.p, NPAR, s->pbf.p);
+    hipLaunchKernelGGL(to_bf16, dim3(unsigned((NPAR + 255) / 256)), dim3(256), 0, 0, s->par.p, s->pbf.p, s->pbft.p);
     HIPCHK(hipGetLastError());
     HIPCHK(hipDeviceSynchronize());
     return MGRW_OK;
@@ -921,16 +1280,18 @@ mgrw_status mgrw_surrogate_fwd_bwd(mgrw_process* p, const float* x, const float*
     surrogate* s = p->sur;
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIPCHK(ensure_rows(s, m));
-    hipLaunchKernelGGL(features_from_f32, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, x, m, s->x0.p);
-    HIPCHK(hipMemcpyAsync(s->kd.p, kd, m * sizeof(float), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(s->y.p, y, m * sizeof(float), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemsetAsync(s->lossd.p, 0, sizeof(double), st));
-    HIPCHK(hipMemsetAsync(s->grad.p, 0, NPAR * sizeof(float), st));
-    forward(s, m, true, st);
-    mgrw_status r = head_train(s, m, 1.0 / double(m), st);
-    if (r != MGRW_OK) return r;
-    r = backward(s, m, st);
-    if (r != MGRW_OK) return r;
+    sbuf<uint16_t> xall(st);
+    HIPCHK(xall.alloc(size_t(m) * K0));
+    hipLaunchKernelGGL(features_from_f32, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, x, m, xall.p);
+    train_src S{};
+    S.x = xall.p;
+    S.kd = kd;
+    S.y = y;
+    S.P = 1;
+    S.ns = m;
+    S.shuffle = 0;
+    train_step(s, S, 0, int(m), 1, 0.0f, st);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(pred, s->pred.p, m * sizeof(float), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(grad, s->grad.p, NPAR * sizeof(float), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(loss, s->lossd.p, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -955,22 +1316,32 @@ mgrw_status mgrw_surrogate_train(mgrw_process* p, const double* mom, int64_t n_e
 
     if (check_device_ptr(mom, "mom", false) != MGRW_OK) return MGRW_ERR_ARG;
 
-    // labels from the exact kernels
-    dbuf<double> wex;
+    // labels y = log(W'/W) from the exact kernels (sample s = e P + k): the
+    // kappa-polynomial evaluation where the process has it (exact up to
+    // rounding, one amplitude program per helicity for all points), else the
+    // point-by-point one; the features once per event (the kappa column is
+    // set per sample in training)
+    sbuf<double> wex(st);
     HIPCHK(wex.alloc(size_t(ns)));
-    mgrw_status r = mgrw_reweight(p, mom, nullptr, n_events, wex.p, nullptr, stream);
+    mgrw_status r = p->proc == MGRW_GG_TTGGG ? mgrw_reweight(p, mom, nullptr, n_events, wex.p, nullptr, stream)
+                                             : mgrw_reweight_kpoly(p, mom, nullptr, n_events, wex.p, nullptr, stream);
     if (r != MGRW_OK) return r;
-    dbuf<float> yall, kdall;
-    dbuf<uint16_t> xall;
+    sbuf<float> yall(st), kdev(st);
+    sbuf<uint16_t> xev(st);
     HIPCHK(yall.alloc(size_t(ns)));
-    HIPCHK(kdall.alloc(size_t(ns)));
-    HIPCHK(xall.alloc(size_t(ns) * K0));
+    HIPCHK(kdev.alloc(size_t(n_events)));
+    HIPCHK(xev.alloc(size_t(n_events) * K0));
     hipLaunchKernelGGL(labels_kernel, dim3(unsigned((ns + 255) / 256)), dim3(256), 0, st, wex.p, P, n_events, yall.p);
-    hipLaunchKernelGGL(features_kernel, dim3(unsigned((ns + 255) / 256)), dim3(256), 0, st, mom, n_ext, n_events,
-                       int64_t(0), P, kappas_of(p), ns, xall.p, kdall.p);
+    hipLaunchKernelGGL(features_kernel, dim3(unsigned((n_events + 255) / 256)), dim3(256), 0, st, mom, n_ext,
+                       n_events, int64_t(0), 1, kappas_of(p), n_events, p->sur_inputs, xev.p, kdev.p);
     HIPCHK(hipGetLastError());
-
-    return train_core(p, xall.p, kdall.p, yall.p, ns, cfg, loss_out, st);
+    train_src S{};
+    S.x = xev.p;
+    S.y = yall.p;
+    S.P = P;
+    S.kappa = kappas_of(p);
+    S.ns = ns;
+    return train_core(p, S, cfg, loss_out, st, p->sur_inputs);
 }
 
 mgrw_status mgrw_surrogate_train_samples(mgrw_process* p, const float* x, const float* kd, const float* y,
@@ -984,16 +1355,17 @@ mgrw_status mgrw_surrogate_train_samples(mgrw_process* p, const float* x, const 
         check_device_ptr(y, "y", false) != MGRW_OK)
         return MGRW_ERR_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    dbuf<uint16_t> xall;
-    dbuf<float> kdall, yall;
+    sbuf<uint16_t> xall(st);
     HIPCHK(xall.alloc(size_t(m) * K0));
-    HIPCHK(kdall.alloc(size_t(m)));
-    HIPCHK(yall.alloc(size_t(m)));
     hipLaunchKernelGGL(features_from_f32, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, x, m, xall.p);
-    HIPCHK(hipMemcpyAsync(kdall.p, kd, size_t(m) * sizeof(float), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(yall.p, y, size_t(m) * sizeof(float), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipGetLastError());
-    return train_core(p, xall.p, kdall.p, yall.p, m, cfg, loss_out, st);
+    train_src S{};
+    S.x = xall.p;
+    S.kd = kd;
+    S.y = y;
+    S.P = 1;
+    S.ns = m;
+    return train_core(p, S, cfg, loss_out, st);
 }
 
 mgrw_status mgrw_reweight_surrogate(mgrw_process* p, const double* mom, const double* w_in, int64_t n_events,
@@ -1031,7 +1403,7 @@ mgrw_status mgrw_reweight_surrogate(mgrw_process* p, const double* mom, const do
         const int64_t ne = std::min(chunk_ev, n_events - e0);
         const int64_t rows = ne * P;
         hipLaunchKernelGGL(features_kernel, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, mom, n_ext,
-                           n_events, e0, 1, kap, ne, xev.p, kdev.p);
+                           n_events, e0, 1, kap, ne, p->sur_inputs, xev.p, kdev.p);
         hipLaunchKernelGGL(mlp_infer_kernel, dim3(unsigned((rows + FR - 1) / FR)), dim3(256), 0, st, xev.p, P,
                            kap, int(rows), e0, n_events, s->pbf.p, s->par.p, w_in, w_out);
     }

@@ -174,6 +174,10 @@ def test_get_option_and_default_rescue_thresholds(L):
     assert L.mgrw_set_option(p._h, 2, 500) == bd.OK
     assert p.rescue_threshold == pytest.approx(5e-4)
     assert L.mgrw_get_option(p._h, 1, ctypes.byref(v)) == bd.OK and v.value == 0
+    assert L.mgrw_get_option(p._h, 5, ctypes.byref(v)) == bd.OK and v.value == 53   # surrogate inputs
+    assert L.mgrw_set_option(p._h, 5, 25) == bd.OK
+    assert L.mgrw_get_option(p._h, 5, ctypes.byref(v)) == bd.OK and v.value == 25
+    assert L.mgrw_set_option(p._h, 5, 30) == bd.ERR_ARG
     assert L.mgrw_get_option(p._h, 99, ctypes.byref(v)) == bd.ERR_ARG
     assert L.mgrw_get_option(p._h, 2, None) == bd.ERR_ARG
     assert L.mgrw_get_option(None, 2, ctypes.byref(v)) == bd.ERR_ARG

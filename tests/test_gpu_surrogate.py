@@ -114,6 +114,35 @@ def test_inference_matches_oracle_network(torch_dev):
         assert np.all(yh[np.isclose(kap, 1.0)] == 0.0)
 
 
+def test_inference_with_the_25_workload_inputs(torch_dev):
+    """With the surrogate restricted to the workload's 25 inputs (momentum
+    components and kappa), the fused inference equals the oracle network on
+    features whose invariant columns are zero."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    params = mlp.init_params(9).astype(np.float32)
+    kap = kappa_points(8)
+    n = 517
+    say(f"case surrogate fused inference, 25 inputs, gg_ttgg n={n}")
+    p = mg.Process("gg_ttgg", "mixed")
+    p.set_params([{"kappa_ttg": float(k)} for k in kap])
+    p.set_surrogate_params(params)
+    p.set_surrogate_inputs(25)
+    mom_np = generate_events("gg_ttgg", n, first_event=6 * 10 ** 5)
+    out, _, fb = p.reweight_surrogate(dev(torch, mom_np), audit_fraction=1e-12, seed=5, max_audit_error=1.0)
+    torch.cuda.synchronize()
+    assert not fb
+    yh = np.log(out.cpu().numpy())
+    x, kd = mlp.features(mom_np, kap)
+    x[:, 25:] = 0.0
+    ye, _ = mlp.forward(params.astype(np.float64), x, kd, emulate_bf16=True)
+    err = rel_l2(yh, ye.reshape(n, len(kap)).T)
+    say(f"  yhat rel-L2 vs bf16-emulating oracle {err:.2e}")
+    assert err < 1e-3
+    with pytest.raises(mg.MgrwError):
+        p.set_surrogate_inputs(30)
+
+
 def test_audit_selection_is_the_counter_hash(torch_dev, trained_ttg):
     """The device-side audit selection is exactly {e : u(seed, 2, e) < f} with
     u the SplitMix64-finaliser draw, recomputed here in Python integers."""
@@ -179,8 +208,11 @@ def test_training_on_closed_form_target(torch_dev):
     pr = pred.cpu().numpy().astype(np.float64)
     ratio = np.mean((pr - yt) ** 2) / np.var(yt)
     say(f"  losses {losses}; held-out error variance / target variance {ratio:.4f}")
-    # the per-epoch mean loss falls, to a few per cent of the target variance
-    assert np.all(np.isfinite(losses)) and losses[-1] < losses[0] and losses[-1] < 0.05 * np.var(y)
+    # the per-epoch mean loss falls by more than a factor 5 (measured: 15, from
+    # 2.3e-5 to 1.6e-6; the first epoch's mean already includes most of the
+    # descent, so the ratio of epoch means understates it) and ends at a few
+    # per cent of the target variance
+    assert np.all(np.isfinite(losses)) and losses[-1] < losses[0] / 5 and losses[-1] < 0.05 * np.var(y)
     # a plain FP64 emulation of the same training reaches about 0.01
     assert ratio < 0.05
 
