@@ -285,8 +285,12 @@ class Emitter:
     external wavefunctions, the t tbar current and the single-gluon row and
     column currents are shared by all groups."""
 
-    def __init__(self, ng, global_leaf_lr=True, kpoly=False, flow_range=None):
+    def __init__(self, ng, global_leaf_lr=True, kpoly=False, flow_range=None, merge_flows=True):
         self.ng = ng
+        # amplitudes of a closing group with the same (flow, sign) pattern over
+        # several flows are summed first and the sum added to those flows once
+        self.merge_flows = merge_flows
+        self.pending = {}
         self.kpoly = kpoly          # accumulate J per power of kappa (J[(k-1)*K + w])
         # (lo, hi): accumulate only the flows lo <= w < hi, into J[w - lo]; diagrams
         # with no term there are left out, and so are the currents only they use
@@ -413,6 +417,7 @@ class Emitter:
 
     def accumulate(self, amp, seq):
         col = diagram_colour(seq)
+        terms = []
         for w, c in sorted(col.items(), key=lambda x: self.flow_index[x[0]]):
             assert c in (1, -1), (seq, w, c)
             j = self.flow_index[w]
@@ -422,9 +427,31 @@ class Emitter:
                 j -= self.flow_range[0]
             if self.kpoly:   # one top-gluon vertex per attached tree: kappa^len(seq)
                 j += (len(seq) - 1) * len(self.flows)
+            terms.append((j, c))
+        if self.merge_flows and len(terms) > 1:
+            # running sum per pattern, normalised so that its first flow enters with +
+            s0 = terms[0][1]
+            key = tuple((j, c * s0) for j, c in terms)
+            name = self.pending.get(key)
+            if name is None:
+                name = self.var("s")
+                self.pending[key] = name
+                self.emit(f"cx<T> {name} = {'' if s0 > 0 else '-'}{amp};")
+            else:
+                self.emit(f"{name} = {name} {'+' if s0 > 0 else '-'} {amp};")
+            return
+        for j, c in terms:
             op = "+" if c > 0 else "-"
             self.emit(f"J[{j}] = J[{j}] {op} {amp};")
             self.n_jterms += 1
+
+    def flush(self):
+        """Add the group's pattern sums to their flows."""
+        for key, name in self.pending.items():
+            for j, c in key:
+                self.emit(f"J[{j}] = J[{j}] {'+' if c > 0 else '-'} {name};")
+                self.n_jterms += 1
+        self.pending = {}
 
     def close_ttg(self, seq, j):
         if not self.wanted(seq):
@@ -492,6 +519,7 @@ class Emitter:
             self.emit("// leaf-only diagrams")
             for seq, j in leaf:
                 self.close_ttg(seq, j)
+            self.flush()
         self.cache = {}
         for U in sorted(groups, key=lambda m: (popcount(m), m)):
             if only is not None and U not in only:
@@ -515,6 +543,7 @@ class Emitter:
                     self.close_ttg(seq, j)
                 else:
                     self.close_root(seq)
+            self.flush()
             self.cache = {}
         return self.lines
 
