@@ -56,6 +56,17 @@ template <typename T> MGRW_HD cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
 // i * a and -i * a (no arithmetic)
 template <typename T> MGRW_HD cx<T> times_i(cx<T> a) { return {-a.im, a.re}; }
 template <typename T> MGRW_HD cx<T> times_mi(cx<T> a) { return {a.im, -a.re}; }
+// acc + a * b and acc - a * b with each real product added to the running sum
+// on its own, so that every product feeds an addition and the device compiler
+// fuses the pair (two fused multiply-adds per component instead of a complex
+// product and a separate addition).  Same operations and counts as
+// `acc + a * b`; only the rounding of the intermediate sums differs.
+template <typename T> MGRW_HD cx<T> cmad(cx<T> a, cx<T> b, cx<T> acc) {
+    return {(acc.re + a.re * b.re) - a.im * b.im, (acc.im + a.re * b.im) + a.im * b.re};
+}
+template <typename T> MGRW_HD cx<T> cmsb(cx<T> a, cx<T> b, cx<T> acc) {
+    return {(acc.re - a.re * b.re) + a.im * b.im, (acc.im - a.re * b.im) - a.im * b.re};
+}
 
 // --- the empty zero ---
 template <typename T> MGRW_HD cx<T> operator+(cx<T> a, zero) { return a; }
@@ -70,6 +81,10 @@ MGRW_HD zero operator+(zero, zero) { return {}; }
 MGRW_HD zero operator-(zero, zero) { return {}; }
 MGRW_HD zero operator-(zero) { return {}; }
 MGRW_HD zero operator*(zero, zero) { return {}; }
+template <typename T> MGRW_HD cx<T> cmad(cx<T> a, cx<T> b, zero) { return a * b; }
+template <typename T> MGRW_HD cx<T> cmsb(cx<T> a, cx<T> b, zero) { return -(a * b); }
+template <typename T, typename Acc> MGRW_HD Acc cmad(zero, cx<T>, Acc acc) { return acc; }
+template <typename T, typename Acc> MGRW_HD Acc cmsb(zero, cx<T>, Acc acc) { return acc; }
 
 // --- four-vectors ---
 template <typename T>
@@ -89,7 +104,7 @@ template <typename T> MGRW_HD r4<T> operator-(r4<T> a, r4<T> b) { return {a.t - 
 // Minkowski products
 template <typename T, typename A, typename B>
 MGRW_HD cx<T> dot(const v4<T, A>& a, const v4<T, B>& b) {
-    return ((a.t * b.t - a.x * b.x) - a.y * b.y) - a.z * b.z;
+    return cmsb(a.z, b.z, cmsb(a.y, b.y, cmsb(a.x, b.x, a.t * b.t)));
 }
 template <typename T, typename A>
 MGRW_HD cx<T> dot(const v4<T, A>& a, const r4<T>& p) {
@@ -123,10 +138,10 @@ MGRW_HD v4<T> vvv(const v4<T, A>& J1, const r4<T>& P1, const v4<T, B>& J2, const
     cx<T> j1b = dot(J1, b) * coup;
     cx<T> j2c = dot(J2, c) * coup;
     v4<T> r;
-    r.t = (j12 * d.t + J2.t * j1b) - J1.t * j2c;
-    r.x = (j12 * d.x + J2.x * j1b) - J1.x * j2c;
-    r.y = (j12 * d.y + J2.y * j1b) - J1.y * j2c;
-    r.z = (j12 * d.z + J2.z * j1b) - J1.z * j2c;
+    r.t = cmsb(J1.t, j2c, cmad(J2.t, j1b, j12 * d.t));
+    r.x = cmsb(J1.x, j2c, cmad(J2.x, j1b, j12 * d.x));
+    r.y = cmsb(J1.y, j2c, cmad(J2.y, j1b, j12 * d.y));
+    r.z = cmsb(J1.z, j2c, cmad(J2.z, j1b, j12 * d.z));
     return r;
 }
 
@@ -150,18 +165,18 @@ MGRW_HD auto vvvv(const v4<T, A>& J1, const v4<T, B>& J2, const v4<T, C>& J3, T 
     using TB = decltype(J1.t * d23 - J3.t * d12);
     using TC = decltype(J1.t * d23 - J2.t * d13);
     vvvv_out<v4<T, TA>, v4<T, TB>, v4<T, TC>> o;
-    o.A.t = J2.t * d13 - J3.t * d12;
-    o.A.x = J2.x * d13 - J3.x * d12;
-    o.A.y = J2.y * d13 - J3.y * d12;
-    o.A.z = J2.z * d13 - J3.z * d12;
-    o.B.t = J1.t * d23 - J3.t * d12;
-    o.B.x = J1.x * d23 - J3.x * d12;
-    o.B.y = J1.y * d23 - J3.y * d12;
-    o.B.z = J1.z * d23 - J3.z * d12;
-    o.C.t = J1.t * d23 - J2.t * d13;
-    o.C.x = J1.x * d23 - J2.x * d13;
-    o.C.y = J1.y * d23 - J2.y * d13;
-    o.C.z = J1.z * d23 - J2.z * d13;
+    o.A.t = cmsb(J3.t, d12, J2.t * d13);
+    o.A.x = cmsb(J3.x, d12, J2.x * d13);
+    o.A.y = cmsb(J3.y, d12, J2.y * d13);
+    o.A.z = cmsb(J3.z, d12, J2.z * d13);
+    o.B.t = cmsb(J3.t, d12, J1.t * d23);
+    o.B.x = cmsb(J3.x, d12, J1.x * d23);
+    o.B.y = cmsb(J3.y, d12, J1.y * d23);
+    o.B.z = cmsb(J3.z, d12, J1.z * d23);
+    o.C.t = cmsb(J2.t, d13, J1.t * d23);
+    o.C.x = cmsb(J2.x, d13, J1.x * d23);
+    o.C.y = cmsb(J2.y, d13, J1.y * d23);
+    o.C.z = cmsb(J2.z, d13, J1.z * d23);
     return o;
 }
 
@@ -173,10 +188,10 @@ MGRW_HD sp<T> row_slash(const sp<T>& a, const v4<T, A>& J) {
     cx<T> jt = J.x + times_i(J.y);  // J1 + i J2
     cx<T> js = J.x - times_i(J.y);  // J1 - i J2
     sp<T> b;
-    b.c0 = a.c2 * jp + a.c3 * jt;
-    b.c1 = a.c2 * js + a.c3 * jm;
-    b.c2 = a.c0 * jm - a.c1 * jt;
-    b.c3 = a.c1 * jp - a.c0 * js;
+    b.c0 = cmad(a.c3, jt, a.c2 * jp);
+    b.c1 = cmad(a.c3, jm, a.c2 * js);
+    b.c2 = cmsb(a.c1, jt, a.c0 * jm);
+    b.c3 = cmsb(a.c0, js, a.c1 * jp);
     return b;
 }
 
@@ -186,10 +201,10 @@ MGRW_HD sp<T> slash_col(const v4<T, A>& J, const sp<T>& v) {
     cx<T> jp = J.t + J.z, jm = J.t - J.z;
     cx<T> jt = J.x + times_i(J.y), js = J.x - times_i(J.y);
     sp<T> b;
-    b.c0 = jm * v.c2 - js * v.c3;
-    b.c1 = jp * v.c3 - jt * v.c2;
-    b.c2 = jp * v.c0 + js * v.c1;
-    b.c3 = jt * v.c0 + jm * v.c1;
+    b.c0 = cmsb(js, v.c3, jm * v.c2);
+    b.c1 = cmsb(jt, v.c2, jp * v.c3);
+    b.c2 = cmad(js, v.c1, jp * v.c0);
+    b.c3 = cmad(jm, v.c1, jt * v.c0);
     return b;
 }
 
@@ -199,10 +214,10 @@ MGRW_HD sp<T> row_prop(const sp<T>& b, const r4<T>& q, T m, T f) {
     T qp = q.t + q.z, qm = q.t - q.z;
     cx<T> qt = {q.x, q.y}, qs = {q.x, -q.y};   // q1 + i q2, q1 - i q2
     sp<T> c;
-    c.c0 = (b.c0 * m + b.c2 * qp) + b.c3 * qt;
-    c.c1 = (b.c1 * m + b.c2 * qs) + b.c3 * qm;
-    c.c2 = (b.c2 * m + b.c0 * qm) - b.c1 * qt;
-    c.c3 = (b.c3 * m + b.c1 * qp) - b.c0 * qs;
+    c.c0 = cmad(b.c3, qt, b.c0 * m + b.c2 * qp);
+    c.c1 = cmad(b.c2, qs, b.c1 * m) + b.c3 * qm;
+    c.c2 = cmsb(b.c1, qt, b.c2 * m + b.c0 * qm);
+    c.c3 = cmsb(b.c0, qs, b.c3 * m + b.c1 * qp);
     return {c.c0 * f, c.c1 * f, c.c2 * f, c.c3 * f};
 }
 
@@ -212,16 +227,16 @@ MGRW_HD sp<T> prop_col(const r4<T>& q, T m, const sp<T>& v, T f) {
     T qp = q.t + q.z, qm = q.t - q.z;
     cx<T> qt = {q.x, q.y}, qs = {q.x, -q.y};
     sp<T> c;
-    c.c0 = (v.c0 * m + v.c2 * qm) - v.c3 * qs;
-    c.c1 = (v.c1 * m + v.c3 * qp) - v.c2 * qt;
-    c.c2 = (v.c2 * m + v.c0 * qp) + v.c1 * qs;
-    c.c3 = (v.c3 * m + v.c0 * qt) + v.c1 * qm;
+    c.c0 = cmsb(v.c3, qs, v.c0 * m + v.c2 * qm);
+    c.c1 = cmsb(v.c2, qt, v.c1 * m + v.c3 * qp);
+    c.c2 = cmad(v.c1, qs, v.c2 * m + v.c0 * qp);
+    c.c3 = cmad(v.c0, qt, v.c3 * m) + v.c1 * qm;
     return {c.c0 * f, c.c1 * f, c.c2 * f, c.c3 * f};
 }
 
 template <typename T>
 MGRW_HD cx<T> row_col(const sp<T>& a, const sp<T>& b) {
-    return ((a.c0 * b.c0 + a.c1 * b.c1) + a.c2 * b.c2) + a.c3 * b.c3;
+    return cmad(a.c3, b.c3, cmad(a.c2, b.c2, cmad(a.c1, b.c1, a.c0 * b.c0)));
 }
 
 // Top-gluon vertex followed by the top propagator, on the row (outgoing-top)
