@@ -231,6 +231,19 @@ qcd_setup_kernel(const double* __restrict__ mom, int64_t n, int64_t e0, int64_t 
     ev[el].skip = skip;
 }
 
+// An event's kinematics record as the generated programs should read it:
+// each value loaded where the program uses it, into vector registers.  The
+// record is wave-uniform, and read through its plain address the compiler
+// loads it into scalar registers ahead of the program and, having too few,
+// spills them to vector lanes (a vector instruction per spill and reload);
+// an opaque copy of the address makes it load each value near its use.
+template <class K>
+__device__ __forceinline__ const K& kin_near_use(const K& k) {
+    const K* p = &k;
+    __asm__ volatile("" : "+s"(p));
+    return *p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -266,7 +279,7 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
             typename Proc::template ext<T>& wf = wfs[threadIdx.x].v;
             Proc::template external<T>(b, hc + lane, wf);
             cx<T> J[Proc::K];
-            Proc::amplitude(wf, k, c, J);
+            Proc::amplitude(wf, kin_near_use(k), c, J);
             acc += double(Proc::colour_sum(J));
         }
         const double me = wave_sum(acc) * Proc::NORM;

@@ -98,8 +98,36 @@ struct v4 {                    // complex four-vector, upper index; Tt = zero fo
 };
 template <typename T> using pol4 = v4<T, zero>;
 
+// Momentum combinations of a three-gluon vertex whose gluon lines carry the
+// incoming momenta P1, P2: d = P1 - P2, b = P1 + 2 P2, c = P2 + 2 P1.  They
+// depend on the event only, so they are formed once per event (in double)
+// rather than once per helicity and point.
+template <typename T>
+struct vvv_mom {
+    r4<T> d, b, c;
+};
+// A top-line momentum q in light-cone form: qp = q0 + q3, qm = q0 - q3, and
+// q1, q2 (again formed once per event).
+template <typename T>
+struct lc4 {
+    T qp, qm, qx, qy;
+};
+
 template <typename T> MGRW_HD r4<T> operator+(r4<T> a, r4<T> b) { return {a.t + b.t, a.x + b.x, a.y + b.y, a.z + b.z}; }
 template <typename T> MGRW_HD r4<T> operator-(r4<T> a, r4<T> b) { return {a.t - b.t, a.x - b.x, a.y - b.y, a.z - b.z}; }
+
+// The vertex and propagator momenta formed in the program, from the
+// gluon-set momenta P1, P2 and a top-line momentum q.
+template <typename T>
+MGRW_HD vvv_mom<T> vvv_mom_of(const r4<T>& P1, const r4<T>& P2) {
+    return {P1 - P2,
+            {P1.t + (P2.t + P2.t), P1.x + (P2.x + P2.x), P1.y + (P2.y + P2.y), P1.z + (P2.z + P2.z)},
+            {P2.t + (P1.t + P1.t), P2.x + (P1.x + P1.x), P2.y + (P1.y + P1.y), P2.z + (P1.z + P1.z)}};
+}
+template <typename T>
+MGRW_HD lc4<T> lc4_of(const r4<T>& q) {
+    return {q.t + q.z, q.t - q.z, q.x, q.y};
+}
 
 // Minkowski products
 template <typename T, typename A, typename B>
@@ -128,15 +156,13 @@ struct sp {
 // off-shell current of two gluon currents J1, J2 carrying incoming momenta P1,
 // P2.  Returns  coup * [(J1.J2)(P1-P2) + (J1.(P1+2P2)) J2 - (J2.(2P1+P2)) J1],
 // where coup = g / (P1+P2)^2 (the colour factor and the constant phase are
-// applied by the caller).
+// applied by the caller); V holds the three momentum combinations.
 template <typename T, typename A, typename B>
-MGRW_HD v4<T> vvv(const v4<T, A>& J1, const r4<T>& P1, const v4<T, B>& J2, const r4<T>& P2, T coup) {
-    r4<T> d = P1 - P2;
-    r4<T> b = {P1.t + (P2.t + P2.t), P1.x + (P2.x + P2.x), P1.y + (P2.y + P2.y), P1.z + (P2.z + P2.z)};
-    r4<T> c = {P2.t + (P1.t + P1.t), P2.x + (P1.x + P1.x), P2.y + (P1.y + P1.y), P2.z + (P1.z + P1.z)};
+MGRW_HD v4<T> vvv(const v4<T, A>& J1, const v4<T, B>& J2, const vvv_mom<T>& V, T coup) {
+    const r4<T>& d = V.d;
     cx<T> j12 = dot(J1, J2) * coup;
-    cx<T> j1b = dot(J1, b) * coup;
-    cx<T> j2c = dot(J2, c) * coup;
+    cx<T> j1b = dot(J1, V.b) * coup;
+    cx<T> j2c = dot(J2, V.c) * coup;
     v4<T> r;
     r.t = cmsb(J1.t, j2c, cmad(J2.t, j1b, j12 * d.t));
     r.x = cmsb(J1.x, j2c, cmad(J2.x, j1b, j12 * d.x));
@@ -210,9 +236,9 @@ MGRW_HD sp<T> slash_col(const v4<T, A>& J, const sp<T>& v) {
 
 // Row spinor times (qslash + m) for a real momentum q, times a real factor.
 template <typename T>
-MGRW_HD sp<T> row_prop(const sp<T>& b, const r4<T>& q, T m, T f) {
-    T qp = q.t + q.z, qm = q.t - q.z;
-    cx<T> qt = {q.x, q.y}, qs = {q.x, -q.y};   // q1 + i q2, q1 - i q2
+MGRW_HD sp<T> row_prop(const sp<T>& b, const lc4<T>& q, T m, T f) {
+    const T qp = q.qp, qm = q.qm;
+    cx<T> qt = {q.qx, q.qy}, qs = {q.qx, -q.qy};   // q1 + i q2, q1 - i q2
     sp<T> c;
     c.c0 = cmad(b.c3, qt, b.c0 * m + b.c2 * qp);
     c.c1 = cmad(b.c2, qs, b.c1 * m) + b.c3 * qm;
@@ -223,9 +249,9 @@ MGRW_HD sp<T> row_prop(const sp<T>& b, const r4<T>& q, T m, T f) {
 
 // (qslash + m) times a column spinor, times a real factor.
 template <typename T>
-MGRW_HD sp<T> prop_col(const r4<T>& q, T m, const sp<T>& v, T f) {
-    T qp = q.t + q.z, qm = q.t - q.z;
-    cx<T> qt = {q.x, q.y}, qs = {q.x, -q.y};
+MGRW_HD sp<T> prop_col(const lc4<T>& q, T m, const sp<T>& v, T f) {
+    const T qp = q.qp, qm = q.qm;
+    cx<T> qt = {q.qx, q.qy}, qs = {q.qx, -q.qy};
     sp<T> c;
     c.c0 = cmsb(v.c3, qs, v.c0 * m + v.c2 * qm);
     c.c1 = cmsb(v.c2, qt, v.c1 * m + v.c3 * qp);
@@ -242,15 +268,24 @@ MGRW_HD cx<T> row_col(const sp<T>& a, const sp<T>& b) {
 // Top-gluon vertex followed by the top propagator, on the row (outgoing-top)
 // side:  coup * a . Jslash . (qslash + m), coup = g kappa / (q^2 - m^2).
 template <typename T, typename A>
-MGRW_HD sp<T> ffv_row(const sp<T>& a, const v4<T, A>& J, const r4<T>& q, T m, T coup) {
+MGRW_HD sp<T> ffv_row(const sp<T>& a, const v4<T, A>& J, const lc4<T>& q, T m, T coup) {
     return row_prop(row_slash(a, J), q, m, coup);
 }
 
 // Top-gluon vertex followed by the top propagator on the column (antitop)
 // side: coup * (qslash + m) . Jslash . v.
 template <typename T, typename A>
-MGRW_HD sp<T> ffv_col(const v4<T, A>& J, const sp<T>& v, const r4<T>& q, T m, T coup) {
+MGRW_HD sp<T> ffv_col(const v4<T, A>& J, const sp<T>& v, const lc4<T>& q, T m, T coup) {
     return prop_col(q, m, slash_col(J, v), coup);
+}
+
+template <typename T, typename A>
+MGRW_HD sp<T> ffv_row(const sp<T>& a, const v4<T, A>& J, const r4<T>& q, T m, T coup) {
+    return ffv_row(a, J, lc4_of(q), m, coup);
+}
+template <typename T, typename A>
+MGRW_HD sp<T> ffv_col(const v4<T, A>& J, const sp<T>& v, const r4<T>& q, T m, T coup) {
+    return ffv_col(J, v, lc4_of(q), m, coup);
 }
 
 // Closing vertex: coup * a . Jslash . v, coup = g kappa.

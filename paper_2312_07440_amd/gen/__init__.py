@@ -9,6 +9,10 @@ QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 CHUNKS = {"gg_ttggg": 4}
 # their double-precision instance: (chunks of closing groups, ranges of colour flows)
 FP64_SPLIT = {"gg_ttggg": (4, 4)}
+# processes evaluated one event per wave, whose programs read the momentum
+# combinations of their vertices from the event record (the one-event-per-lane
+# kernel keeps the record in per-lane LDS, where a larger record costs occupancy)
+VERTEX_KIN = {"gg_ttgg", "gg_ttggg"}
 
 
 def translation_units(names=None):
@@ -39,7 +43,8 @@ def generate(outdir=None, procs=None, force=False):
            "    const qcd_launch& a, double* out, double* me0, hipStream_t s)")
     for name, ng in (procs or QCD_PROCESSES).items():
         nch = CHUNKS.get(name, 1)
-        src, em = emit_process(name, ng, chunks=nch, fp64_split=FP64_SPLIT.get(name))
+        src, em = emit_process(name, ng, chunks=nch, fp64_split=FP64_SPLIT.get(name),
+                               vertex_kin=name in VERTEX_KIN)
         put(os.path.join(outdir, f"{name}.inc"), src)
         head = f"// Generated: kernel instantiations for {name}.\n" \
                f'#include "../mgrw_kernels.h"\n#include "{name}.inc"\nnamespace mgrw {{\n'

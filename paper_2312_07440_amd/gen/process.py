@@ -285,8 +285,13 @@ class Emitter:
     external wavefunctions, the t tbar current and the single-gluon row and
     column currents are shared by all groups."""
 
-    def __init__(self, ng, global_leaf_lr=True, kpoly=False, flow_range=None, merge_flows=True):
+    def __init__(self, ng, global_leaf_lr=True, kpoly=False, flow_range=None, merge_flows=True,
+                 vertex_kin=False):
         self.ng = ng
+        # vertex_kin: three-gluon vertices and top-line propagators read their
+        # momentum combinations from the event record (V, QL, QR) instead of
+        # forming them from the gluon-set momenta P in the program
+        self.vertex_kin = vertex_kin
         # amplitudes of a closing group with the same (flow, sign) pattern over
         # several flows are summed first and the sum added to those flows once
         self.merge_flows = merge_flows
@@ -298,10 +303,13 @@ class Emitter:
         self.full = (1 << ng) - 1
         self.lines = []
         self.nvar = 0
-        self.P_needed = set()      # incoming momentum sums entering three-gluon vertices
+        self.P_needed = set()      # incoming momentum sums entering the program (without vertex_kin)
+        self.V_needed = set()      # (S1, S2) of three-gluon vertices: P1 - P2, P1 + 2 P2, P2 + 2 P1
+        self.QL_needed = set()     # light-cone top-side propagator momenta (with vertex_kin)
+        self.QR_needed = set()
         self.iP_needed = set()     # 1/P^2 of internal gluon lines
-        self.qL_needed = set()     # top-side propagators: q = p_t - P(S)
-        self.qR_needed = set()     # antitop-side propagators: q = P(S) - p_tbar
+        self.qL_needed = set()     # top-side propagators: q = p_t - P(S), and 1/(q^2 - m^2)
+        self.qR_needed = set()     # antitop-side propagators: q = P(S) - p_tbar, and 1/(q^2 - m^2)
         self.flows = flows(ng)
         self.flow_index = {w: i for i, w in enumerate(self.flows)}
         self.n_amp = 0
@@ -324,6 +332,15 @@ class Emitter:
             return self.cache[key]
         return self.global_cache.get(key)
 
+    def vmom(self, t):
+        """Momentum argument of the three-gluon vertex joining t's two subtrees."""
+        m1, m2 = t.kids[0].mask, t.kids[1].mask
+        if self.vertex_kin:
+            self.V_needed.add((m1, m2))
+            return f"k.V{m1}_{m2}"
+        self.P_needed |= {m1, m2}
+        return f"vvv_mom_of(k.P{m1}, k.P{m2})"
+
     # ---- gluon trees
     def tree(self, t):
         key = "T:" + t.key
@@ -337,11 +354,8 @@ class Emitter:
         kids = [self.tree(k) for k in t.kids]
         self.iP_needed.add(t.mask)
         if t.kind == "v3":
-            for k in t.kids:
-                self.P_needed.add(k.mask)
             name = self.var("c")
-            self.emit(f"const v4<T> {name} = vvv({kids[0]}, k.P{t.kids[0].mask}, {kids[1]}, "
-                      f"k.P{t.kids[1].mask}, c.g * k.iP{t.mask});")
+            self.emit(f"const v4<T> {name} = vvv({kids[0]}, {kids[1]}, {self.vmom(t)}, c.g * k.iP{t.mask});")
             self.counts["vvv"] += 1
             self.cache[key] = name
             return name
@@ -368,9 +382,14 @@ class Emitter:
         for t in seq:
             mask |= t.mask
         self.qL_needed.add(mask)
-        self.P_needed.add(mask)
+        if self.vertex_kin:
+            self.QL_needed.add(mask)
+            q = f"k.QL{mask}"
+        else:
+            self.P_needed.add(mask)
+            q = f"k.pt - k.P{mask}"
         name = self.var("l")
-        self.emit(f"const sp<T> {name} = ffv_row({prev}, {cur}, k.pt - k.P{mask}, k.mt, c.gk * k.iqL{mask});")
+        self.emit(f"const sp<T> {name} = ffv_row({prev}, {cur}, {q}, k.mt, c.gk * k.iqL{mask});")
         self.counts["ffv_row"] += 1
         glob = self.global_leaf_lr and len(seq) == 1 and seq[0].kind == "leaf"
         (self.global_cache if glob else self.cache)[key] = name
@@ -390,9 +409,14 @@ class Emitter:
         for t in seq:
             mask |= t.mask
         self.qR_needed.add(mask)
-        self.P_needed.add(mask)
+        if self.vertex_kin:
+            self.QR_needed.add(mask)
+            q = f"k.QR{mask}"
+        else:
+            self.P_needed.add(mask)
+            q = f"k.P{mask} - k.ptb"
         name = self.var("r")
-        self.emit(f"const sp<T> {name} = ffv_col({cur}, {nxt}, k.P{mask} - k.ptb, k.mt, c.gk * k.iqR{mask});")
+        self.emit(f"const sp<T> {name} = ffv_col({cur}, {nxt}, {q}, k.mt, c.gk * k.iqR{mask});")
         self.counts["ffv_col"] += 1
         glob = self.global_leaf_lr and len(seq) == 1 and seq[0].kind == "leaf"
         (self.global_cache if glob else self.cache)[key] = name
@@ -471,11 +495,8 @@ class Emitter:
         jtt = self.tt_current()
         kids = [self.tree(k) for k in t.kids]
         if t.kind == "v3":
-            for k in t.kids:
-                self.P_needed.add(k.mask)
             a = self.var("a")
-            self.emit(f"const cx<T> {a} = dot({jtt}, vvv({kids[0]}, k.P{t.kids[0].mask}, {kids[1]}, "
-                      f"k.P{t.kids[1].mask}, c.g));")
+            self.emit(f"const cx<T> {a} = dot({jtt}, vvv({kids[0]}, {kids[1]}, {self.vmom(t)}, c.g));")
             self.counts["vvv_amp"] += 1
             self.n_amp += 1
             self.accumulate(a, seq)
@@ -594,7 +615,7 @@ def bf16_split_table(num, kp):
     return hi, lo
 
 
-def emit_process(name, ng, chunks=1, fp64_split=None):
+def emit_process(name, ng, chunks=1, fp64_split=None, vertex_kin=False):
     """C++ source of the process struct for g g -> t tbar + (ng-2) g.
 
     With chunks > 1 the per-helicity program is split into that many
@@ -607,18 +628,24 @@ def emit_process(name, ng, chunks=1, fp64_split=None):
     accumulated into that range only (J[w - R K/nfr]).  A diagram with terms in
     several ranges, and the currents it needs, appear in each of them; in
     exchange only K/nfr flow amplitudes are live at a time, which is what
-    lets the program run in double precision."""
+    lets the program run in double precision.
+
+    vertex_kin: the programs (not the kappa-polynomial one) read the momentum
+    combinations of their vertices from the event record."""
     from math import factorial, gcd
-    em = Emitter(ng)
+    em = Emitter(ng, vertex_kin=vertex_kin)
     if chunks > 1:
         parts = split_groups(ng, chunks)
         part_ems = []
         for p in parts:
-            e = Emitter(ng)
+            e = Emitter(ng, vertex_kin=vertex_kin)
             e.program(set(p))
             part_ems.append(e)
         for e in part_ems:
             em.P_needed |= e.P_needed
+            em.V_needed |= e.V_needed
+            em.QL_needed |= e.QL_needed
+            em.QR_needed |= e.QR_needed
             em.iP_needed |= e.iP_needed
             em.qL_needed |= e.qL_needed
             em.qR_needed |= e.qR_needed
@@ -638,12 +665,22 @@ def emit_process(name, ng, chunks=1, fp64_split=None):
         parts64 = split_groups(ng, nch64)
         for c, p in enumerate(parts64):
             for r in range(nfr):
-                e = Emitter(ng, flow_range=(r * kr, (r + 1) * kr))
+                e = Emitter(ng, flow_range=(r * kr, (r + 1) * kr), vertex_kin=vertex_kin)
                 e.program(set(p))
                 fr_ems[(c, r)] = (e, p)
                 # every kinematic quantity the split program needs is in kin<T>
-                assert e.P_needed <= em.P_needed and e.iP_needed <= em.iP_needed
+                assert e.V_needed <= em.V_needed and e.iP_needed <= em.iP_needed
+                assert e.P_needed <= em.P_needed
+                assert e.QL_needed <= em.QL_needed and e.QR_needed <= em.QR_needed
                 assert e.qL_needed <= em.qL_needed and e.qR_needed <= em.qR_needed
+    ek = None
+    if chunks == 1:
+        # kappa-polynomial form of the same diagrams (momenta from P in the program)
+        ek = Emitter(ng, kpoly=True)
+        kbody = ek.program()
+        assert ek.iP_needed <= em.iP_needed
+        assert ek.qL_needed <= em.qL_needed and ek.qR_needed <= em.qR_needed
+        em.P_needed |= ek.P_needed
     K = len(em.flows)
     next_ = ng + 2
     cf = colour_matrix_loops(ng)
@@ -654,6 +691,9 @@ def emit_process(name, ng, chunks=1, fp64_split=None):
     num = [[int(x * den) for x in row] for row in cf]
 
     P_masks = sorted(em.P_needed)
+    V_pairs = sorted(em.V_needed)
+    QL_masks = sorted(em.QL_needed)
+    QR_masks = sorted(em.QR_needed)
     iP_masks = sorted(em.iP_needed)
     qL_masks = sorted(em.qL_needed)
     qR_masks = sorted(em.qR_needed)
@@ -675,14 +715,24 @@ def emit_process(name, ng, chunks=1, fp64_split=None):
     w(f"  static constexpr int NDIAG = {n_diagrams(ng)};")
     w(f"  static constexpr int CF_DEN = {den};")
     w(f"  static constexpr double NORM = 1.0 / (4.0 * 64.0 * {factorial(ng - 2)}.0 * {den}.0);")
-    w("  // Helicity-independent kinematics of one event: incoming momentum sums of")
-    w("  // gluon sets, the top and antitop momenta, and inverse propagator")
-    w("  // denominators formed in double precision.")
+    w("  // Helicity-independent kinematics of one event, formed in double precision")
+    w("  // and rounded once: incoming momentum sums P of gluon sets and the top and")
+    w("  // antitop momenta (for programs that form their vertex momenta), the")
+    w("  // momentum combinations of three-gluon vertices (V<S1>_<S2>) and the top-line")
+    w("  // propagator momenta in light-cone form (QL, QR) for programs that read them,")
+    w("  // and the inverse propagator denominators.")
     w("  template <typename T> struct kin {")
     w("    T mt;")
-    w("    r4<T> pt, ptb;")
+    if P_masks:
+        w("    r4<T> pt, ptb;")
     for m in P_masks:
         w(f"    r4<T> P{m};")
+    for m1, m2 in V_pairs:
+        w(f"    vvv_mom<T> V{m1}_{m2};")
+    for m in QL_masks:
+        w(f"    lc4<T> QL{m};")
+    for m in QR_masks:
+        w(f"    lc4<T> QR{m};")
     for m in iP_masks:
         w(f"    T iP{m};")
     for m in qL_masks:
@@ -703,27 +753,33 @@ def emit_process(name, ng, chunks=1, fp64_split=None):
     w("  template <typename T, typename P>")
     w("  static MGRW_HD void kinematics(const P& p, double mt, kin<T>& k) {")
     w("    k.mt = T(mt);")
-    w("    k.pt = {T(p[2][0]), T(p[2][1]), T(p[2][2]), T(p[2][3])};")
-    w("    k.ptb = {T(p[3][0]), T(p[3][1]), T(p[3][2]), T(p[3][3])};")
+    if P_masks:
+        w("    k.pt = {T(p[2][0]), T(p[2][1]), T(p[2][2]), T(p[2][3])};")
+        w("    k.ptb = {T(p[3][0]), T(p[3][1]), T(p[3][2]), T(p[3][3])};")
     w("    double kin_in[NG][4];")
     for i, ip in enumerate(GLUON_PARTICLE[:ng]):
         sgn = "" if ip < 2 else "-"
         w(f"    for (int m = 0; m < 4; ++m) kin_in[{i}][m] = {sgn}p[{ip}][m];")
-    allm = sorted(set(P_masks) | set(iP_masks) | set(qL_masks) | set(qR_masks))
+    allm = sorted(set(P_masks) | {m for pr in V_pairs for m in pr} | set(iP_masks) | set(qL_masks) | set(qR_masks))
     for m in allm:
         terms = " + ".join(f"kin_in[{i}][m]" for i in bits(m))
         w(f"    double S{m}[4]; for (int m = 0; m < 4; ++m) S{m}[m] = {terms};")
     for m in P_masks:
         w(f"    k.P{m} = {{T(S{m}[0]), T(S{m}[1]), T(S{m}[2]), T(S{m}[3])}};")
+    for m1, m2 in V_pairs:
+        w(f"    {{ double d[4], b[4], c[4]; for (int m = 0; m < 4; ++m) {{ d[m] = S{m1}[m] - S{m2}[m]; "
+          f"b[m] = S{m1}[m] + 2.0 * S{m2}[m]; c[m] = S{m2}[m] + 2.0 * S{m1}[m]; }}")
+        w(f"      k.V{m1}_{m2} = {{{{T(d[0]), T(d[1]), T(d[2]), T(d[3])}}, {{T(b[0]), T(b[1]), T(b[2]), T(b[3])}}, "
+          f"{{T(c[0]), T(c[1]), T(c[2]), T(c[3])}}}}; }}")
     for m in iP_masks:
         w(f"    k.iP{m} = T(1.0 / (((S{m}[0] * S{m}[0] - S{m}[1] * S{m}[1]) - S{m}[2] * S{m}[2]) - "
           f"S{m}[3] * S{m}[3]));")
-    for m in qL_masks:
-        w(f"    {{ double q[4]; for (int m = 0; m < 4; ++m) q[m] = p[2][m] - S{m}[m];")
-        w(f"      k.iqL{m} = T(1.0 / ((((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1]) - q[2] * q[2]) - mt * mt)); }}")
-    for m in qR_masks:
-        w(f"    {{ double q[4]; for (int m = 0; m < 4; ++m) q[m] = S{m}[m] - p[3][m];")
-        w(f"      k.iqR{m} = T(1.0 / ((((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1]) - q[2] * q[2]) - mt * mt)); }}")
+    for side, m_list, qexpr in (("L", qL_masks, "p[2][m] - S{m}[m]"), ("R", qR_masks, "S{m}[m] - p[3][m]")):
+        for m in m_list:
+            w(f"    {{ double q[4]; for (int m = 0; m < 4; ++m) q[m] = {qexpr.format(m=m)};")
+            if m in (QL_masks if side == "L" else QR_masks):
+                w(f"      k.Q{side}{m} = {{T(q[0] + q[3]), T(q[0] - q[3]), T(q[1]), T(q[2])}};")
+            w(f"      k.iq{side}{m} = T(1.0 / ((((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1]) - q[2] * q[2]) - mt * mt)); }}")
     w("  }")
     w("  template <typename T, typename P>")
     w("  static MGRW_HD void external_basis(const P& p, double mt, basis<T>& b) {")
@@ -797,8 +853,6 @@ def emit_process(name, ng, chunks=1, fp64_split=None):
         w("  }")
     if body is not None:
         # kappa-polynomial form of the same diagrams: J split by power of kappa
-        ek = Emitter(ng, kpoly=True)
-        kbody = ek.program()
         w("  // Same diagrams at unit couplings, J[(k-1)*K + w] collecting the diagrams")
         w("  // with k top-gluon vertices: J(g, kappa) = g^NG sum_k kappa^k J_k.")
         w("  // J: a pointer, or an accessor object with operator[] (entries kept partly")
