@@ -25,16 +25,17 @@ ee5a_setup_kernel(const double* __restrict__ mom, int64_t n, int64_t e0, int64_t
     ee_5a::setup(p, ev[el]);
 }
 
+// Events 0 .. nb - 1 of a chunk: records ev, and w_in, out, me0_out, passed
+// from the chunk's first event on (out and me0_out keep the stride n).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-ee5a_wave_kernel(const ee_5a::event<T>* __restrict__ ev, int64_t e0, int64_t nb, const double* __restrict__ w_in,
-                 int64_t n, qed_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
+ee5a_wave_kernel(const ee_5a::event<T>* __restrict__ ev, const double* __restrict__ w_in, int64_t nb, int64_t n,
+                 qed_launch a, double* __restrict__ out, double* __restrict__ me0_out) {
     static_assert(ee_5a::NLIVE == 64, "one live helicity configuration per lane");
-    const int64_t el = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (el >= nb) return;   // whole wave; no barriers below
-    const int64_t e = e0 + el;
+    const int64_t e = int64_t(blockIdx.x) * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (e >= nb) return;   // whole wave; no barriers below
     const int lane = threadIdx.x & 63;
-    const ee_5a::event<T>& d = ev[el];
+    const ee_5a::event<T>& d = ev[e];
     const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
     const double scale = d.flux * ee_5a::NORM;
     double me0 = 0.0;
@@ -89,8 +90,10 @@ hipError_t launch(const double* mom, const double* w_in, int64_t n, const qed_la
         hipLaunchKernelGGL((ee5a_setup_kernel<T>), dim3(unsigned((nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                            mom, n, e0, nb, ev);
         mark(a.t0, s);
+        // the chunk's inputs and outputs are passed from its first event on
         hipLaunchKernelGGL((ee5a_wave_kernel<T>), dim3(unsigned((nb + kBlock / 64 - 1) / (kBlock / 64))),
-                           dim3(kBlock), 0, s, ev, e0, nb, w_in, n, a, out, me0);
+                           dim3(kBlock), 0, s, ev, w_in ? w_in + e0 : w_in, nb, n, a, out + e0,
+                           me0 ? me0 + e0 : me0);
         mark(a.t1, s);
         err = hipGetLastError();
     }
