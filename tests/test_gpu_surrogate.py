@@ -143,6 +143,21 @@ def test_inference_with_the_25_workload_inputs(torch_dev):
         p.set_surrogate_inputs(30)
 
 
+def audit_selected(n, f, seed):
+    """{e : u(seed, 2, e) < f} with u the SplitMix64-finaliser draw, in Python
+    integers."""
+    M = (1 << 64) - 1
+    G = 0x9E3779B97F4A7C15
+
+    def mix(z):
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    h0 = mix((seed + G * 3) & M)
+    return np.array([((mix((h0 + G * (e + 1)) & M) >> 11) + 0.5) * 2.0 ** -53 < f for e in range(n)])
+
+
 def test_audit_selection_is_the_counter_hash(torch_dev, trained_ttg):
     """The device-side audit selection is exactly {e : u(seed, 2, e) < f} with
     u the SplitMix64-finaliser draw, recomputed here in Python integers."""
@@ -155,18 +170,45 @@ def test_audit_selection_is_the_counter_hash(torch_dev, trained_ttg):
     out, st, _ = p.reweight_surrogate(mom, audit_fraction=f, seed=seed, max_audit_error=1.0)
     torch.cuda.synchronize()
     audited = np.all(out.cpu().numpy() != pure.cpu().numpy(), axis=0)
-    M = (1 << 64) - 1
-    G = 0x9E3779B97F4A7C15
-
-    def mix(z):
-        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
-        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
-        return z ^ (z >> 31)
-
-    h0 = mix((seed + G * 3) & M)
-    expect = np.array([((mix((h0 + G * (e + 1)) & M) >> 11) + 0.5) * 2.0 ** -53 < f for e in range(n)])
+    expect = audit_selected(n, f, seed)
     assert np.array_equal(audited, expect)
     assert int(st[0, 4]) == int(expect.sum())
+
+
+def test_audit_with_zero_input_weights(torch_dev, trained_ttg):
+    """Audited events with input weight 0 have exact and surrogate weights 0:
+    they add nothing to the control variate and stay out of the relative-error
+    statistics, which remain finite, so they neither hide a bad surrogate nor
+    switch a good one off."""
+    torch = torch_dev
+    p, _ = trained_ttg
+    n, f, seed = 20000, 0.05, 5
+    say(f"case surrogate audit with zero input weights n={n}")
+    mom = dev(torch, generate_events("gg_ttg", n))
+    w_np = np.random.default_rng(3).uniform(0.5, 2.0, n)
+    w_np[::7] = 0.0
+    w = dev(torch, w_np)
+    exact = p.reweight(mom, w_in=w).cpu().numpy()
+    pure, _, _ = p.reweight_surrogate(mom, w_in=w, audit_fraction=1e-12, seed=seed, max_audit_error=1.0)
+    out, st, fb = p.reweight_surrogate(mom, w_in=w, audit_fraction=f, seed=seed, max_audit_error=1.0)
+    torch.cuda.synchronize()
+    pure, out = pure.cpu().numpy(), out.cpu().numpy()
+    sel, zero = audit_selected(n, f, seed), w_np == 0.0
+    assert (sel & zero).sum() > 0
+    assert not fb and np.all(np.isfinite(st))
+    assert int(st[0, 4]) == int(sel.sum())
+    assert np.array_equal(out[:, sel], exact[:, sel])
+    assert np.array_equal(out[:, ~sel], pure[:, ~sel])
+    assert np.all(out[:, zero] == 0.0)
+    use = sel & ~zero
+    err = np.abs(pure[:, use] / exact[:, use] - 1)
+    assert np.allclose(st[:, 2], err.mean(axis=1), rtol=1e-8)
+    assert np.allclose(st[:, 3], err.std(axis=1, ddof=1) / np.sqrt(use.sum()), rtol=1e-6)
+    # with the error bound below the audit's mean error the exact path answers
+    out2, _, fb2 = p.reweight_surrogate(mom, w_in=w, audit_fraction=f, seed=seed,
+                                        max_audit_error=0.5 * float(st[:, 2].min()))
+    assert fb2
+    assert np.array_equal(out2.cpu().numpy(), exact)
 
 
 def ee_mumu_ratio_samples(n, first_event):
