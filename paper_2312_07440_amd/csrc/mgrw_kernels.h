@@ -236,7 +236,8 @@ qcd_setup_kernel(const double* __restrict__ mom, int64_t n, int64_t e0, int64_t 
 // record is wave-uniform, and read through its plain address the compiler
 // loads it into scalar registers ahead of the program and, having too few,
 // spills them to vector lanes (a vector instruction per spill and reload);
-// an opaque copy of the address makes it load each value near its use.
+// an opaque copy of the address makes it load each value near its use.  The
+// address must be wave-uniform (it is held in scalar registers).
 template <class K>
 __device__ __forceinline__ const K& kin_near_use(const K& k) {
     const K* p = &k;
