@@ -299,10 +299,10 @@ template <typename T>
 MGRW_HD v4<T> vector_current(const sp<T>& a, const sp<T>& b) {
     // upper-right block sigma^mu = (1, s), lower-left sigmabar^mu = (1, -s)
     v4<T> j;
-    j.t = (a.c0 * b.c2 + a.c1 * b.c3) + (a.c2 * b.c0 + a.c3 * b.c1);
-    j.x = (a.c0 * b.c3 + a.c1 * b.c2) - (a.c2 * b.c1 + a.c3 * b.c0);
-    j.y = times_i(a.c1 * b.c2 - a.c0 * b.c3) + times_i(a.c2 * b.c1 - a.c3 * b.c0);
-    j.z = (a.c0 * b.c2 - a.c1 * b.c3) - (a.c2 * b.c0 - a.c3 * b.c1);
+    j.t = cmad(a.c3, b.c1, cmad(a.c2, b.c0, cmad(a.c1, b.c3, a.c0 * b.c2)));
+    j.x = cmsb(a.c3, b.c0, cmsb(a.c2, b.c1, cmad(a.c1, b.c2, a.c0 * b.c3)));
+    j.y = times_i(cmsb(a.c3, b.c0, cmad(a.c2, b.c1, cmsb(a.c0, b.c3, a.c1 * b.c2))));
+    j.z = cmad(a.c3, b.c1, cmsb(a.c2, b.c0, cmsb(a.c1, b.c3, a.c0 * b.c2)));
     return j;
 }
 

@@ -314,8 +314,9 @@ class Emitter:
         self.flow_index = {w: i for i, w in enumerate(self.flows)}
         self.n_amp = 0
         self.n_jterms = 0
-        self.counts = {"vvv": 0, "vvvv": 0, "ffv_row": 0, "ffv_col": 0, "ffv_amp": 0, "vvv_amp": 0,
-                       "vvvv_amp": 0, "tt_current": 0}
+        self.counts = {"vvv": 0, "vvvv": 0, "ffv_row": 0, "ffv_col": 0, "ffv_amp": 0, "vector_current": 0,
+                       "vvv_amp": 0, "vvvv_amp": 0, "tt_current": 0}
+        self.lr_uses, self.vcur = {}, {}
         self.global_cache = {}
         self.cache = {}
         self.global_leaf_lr = global_leaf_lr
@@ -483,10 +484,35 @@ class Emitter:
         left, right = self.L(seq[:j]), self.R(seq[j + 1:])
         cur = self.tree(seq[j])
         a = self.var("a")
-        self.emit(f"const cx<T> {a} = ffv_amp({left}, {cur}, {right}, c.gk);")
+        pair = self.lr_key(seq, j)
+        if self.lr_uses.get(pair, 0) >= 2:
+            # the pair closes several gluon trees in this group: its vector
+            # current ubar_L gamma^mu v_R is formed once, each closure is a dot
+            v = self.vcur.get(pair)
+            if v is None:
+                v = self.var("v")
+                self.emit(f"const v4<T> {v} = vector_current({left}, {right});")
+                self.counts["vector_current"] += 1
+                self.vcur[pair] = v
+            self.emit(f"const cx<T> {a} = dot({cur}, {v}) * c.gk;")
+        else:
+            self.emit(f"const cx<T> {a} = ffv_amp({left}, {cur}, {right}, c.gk);")
         self.counts["ffv_amp"] += 1
         self.n_amp += 1
         self.accumulate(a, seq)
+
+    @staticmethod
+    def lr_key(seq, j):
+        return (tuple(t.key for t in seq[:j]), tuple(t.key for t in seq[j + 1:]))
+
+    def count_pairs(self, items):
+        """Uses of each (row current, column current) pair by the top-vertex
+        closures of one group."""
+        self.lr_uses, self.vcur = {}, {}
+        for seq, j in items:
+            if self.wanted(seq):
+                k = self.lr_key(seq, j)
+                self.lr_uses[k] = self.lr_uses.get(k, 0) + 1
 
     def close_root(self, seq):
         if not self.wanted(seq):
@@ -538,6 +564,7 @@ class Emitter:
         leaf.sort(key=lambda x: ([t.key for t in x[0][x[1] + 1:]], [t.key for t in x[0]]))
         if only is None or "leaf" in only:
             self.emit("// leaf-only diagrams")
+            self.count_pairs(leaf)
             for seq, j in leaf:
                 self.close_ttg(seq, j)
             self.flush()
@@ -559,6 +586,7 @@ class Emitter:
             items.sort(key=lambda it: (anchor(it), it[0], [t.key for t in it[1]]))
             self.emit("MGRW_SCHED_BARRIER();")
             self.emit(f"// closing trees over gluons {bits(U)}")
+            self.count_pairs([(seq, j) for kind, seq, j in items if kind == "ttg"])
             for kind, seq, j in items:
                 if kind == "ttg":
                     self.close_ttg(seq, j)
