@@ -81,7 +81,7 @@ void me_events_split(const double* mom, int64_t n, double mt, const mgrw::qcd_po
         mgrw::qcd_event<Proc, double> ev;
         ev.setup(p, mt);
         for (int kp = 0; kp < npts; ++kp) {
-            typename Proc::template coup<double> c = {pts[kp].gs, pts[kp].gs2, pts[kp].gk};
+            const auto c = Proc::template couplings<double>(pts[kp].gs, pts[kp].gs2, pts[kp].gk);
             double acc = 0.0;
             for (int h = 0; h < Proc::NHEL; ++h) {
                 typename Proc::template ext<double> w;
@@ -91,7 +91,7 @@ void me_events_split(const double* mom, int64_t n, double mt, const mgrw::qcd_po
                 fr_all<Proc, 0>(w, ev.k, c, J);
                 acc += Proc::colour_sum(J);
             }
-            me[int64_t(kp) * n + e] = acc * Proc::NORM;
+            me[int64_t(kp) * n + e] = acc * Proc::point_norm(pts[kp].gs);
         }
     }
 }

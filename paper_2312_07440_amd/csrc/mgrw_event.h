@@ -29,7 +29,7 @@ struct qcd_point {
 // letting them be hoisted into registers for the whole loop.
 template <class Proc, typename T, typename KN, typename BS>
 MGRW_HD double point_me(const KN& k, const BS& b, const qcd_point& pt) {
-    typename Proc::template coup<T> c = {T(pt.gs), T(pt.gs2), T(pt.gk)};
+    const auto c = Proc::template couplings<T>(pt.gs, pt.gs2, pt.gk);
     double acc = 0.0;
 #if defined(__HIP_DEVICE_COMPILE__)
 #pragma unroll 1
@@ -44,7 +44,7 @@ MGRW_HD double point_me(const KN& k, const BS& b, const qcd_point& pt) {
         Proc::amplitude(w, k, c, J);
         acc += double(Proc::colour_sum(J));
     }
-    return acc * Proc::NORM;
+    return acc * Proc::point_norm(pt.gs);
 }
 
 // ------------------------------------------------ kappa-polynomial form

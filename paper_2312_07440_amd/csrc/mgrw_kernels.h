@@ -268,7 +268,7 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
 #pragma unroll 1
     for (int kp = 0; kp < a.npts; ++kp) {
         const qcd_point pt = a.pts[kp];
-        typename Proc::template coup<T> c = {T(pt.gs), T(pt.gs2), T(pt.gk)};
+        const auto c = Proc::template couplings<T>(pt.gs, pt.gs2, pt.gk);
         double acc = 0.0;
 #pragma unroll 1
         for (int hc = 0; hc < Proc::NHEL; hc += 64) {
@@ -283,7 +283,7 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
             Proc::amplitude(wf, kin_near_use(k), c, J);
             acc += double(Proc::colour_sum(J));
         }
-        const double me = wave_sum(acc) * Proc::NORM;
+        const double me = wave_sum(acc) * Proc::point_norm(pt.gs);
         if (kp == 0) {
             me0 = me;
             if (lane == 0) {
@@ -464,7 +464,7 @@ qcd_rescue_kernel(const double* __restrict__ mom, const int64_t* __restrict__ li
 #pragma unroll 1
             for (int kp = 0; kp < a.npts; ++kp) {
                 const qcd_point pt = a.pts[kp];
-                typename Proc::template coup<double> c = {pt.gs, pt.gs2, pt.gk};
+                const auto c = Proc::template couplings<double>(pt.gs, pt.gs2, pt.gk);
                 double acc = 0.0;
 #pragma unroll 1
                 for (int hc = 0; hc < Proc::NHEL; hc += 64) {
@@ -476,7 +476,7 @@ qcd_rescue_kernel(const double* __restrict__ mom, const int64_t* __restrict__ li
                         acc += Proc::colour_sum(J);
                     }
                 }
-                const double me = wave_sum(acc) * Proc::NORM;
+                const double me = wave_sum(acc) * Proc::point_norm(pt.gs);
                 if (kp == 0) {
                     me0 = me;
                     if (lane == 0) {
@@ -657,7 +657,7 @@ qcd_part_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
 #pragma unroll 1
     for (int kp = 0; kp < a.npts; ++kp) {
         const qcd_point pt = a.pts[kp];
-        typename Proc::template coup<T> c = {T(pt.gs), T(pt.gs2), T(pt.gk)};
+        const auto c = Proc::template couplings<T>(pt.gs, pt.gs2, pt.gk);
         double acc = 0.0;
 #pragma unroll 1
         for (int hc = 0; hc < NH; hc += 64) {
@@ -686,7 +686,7 @@ qcd_part_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
             }
         }
         if constexpr (LAST) {
-            const double me = wave_sum(acc) * Proc::NORM;
+            const double me = wave_sum(acc) * Proc::point_norm(pt.gs);
             if (kp == 0) {
                 me0 = me;
                 if (lane == 0) {
@@ -818,7 +818,7 @@ qcd_colour_mfma_kernel(const float* __restrict__ jbuf, int64_t e0, int64_t nb, c
         __syncthreads();
         double me = 0.0;
         for (int i = 0; i < kBlock / 64; ++i) me += part[i];
-        me *= Proc::NORM;
+        me *= Proc::point_norm(a.pts[kp].gs);
         __syncthreads();   // part[] is rewritten for the next point
         if (threadIdx.x == 0) {
             const int64_t e = e0 + el;
@@ -897,7 +897,7 @@ qcd_fr_kernel(const event_data<Proc, double>* __restrict__ ev, const unsigned lo
 #pragma unroll 1
     for (int kp = 0; kp < a.npts; ++kp) {
         const qcd_point pt = a.pts[kp];
-        typename Proc::template coup<double> c = {pt.gs, pt.gs2, pt.gk};
+        const auto c = Proc::template couplings<double>(pt.gs, pt.gs2, pt.gk);
 #pragma unroll 1
         for (int hc = 0; hc < NH; hc += 64) {
             __asm__ volatile("" ::: "memory");
@@ -971,7 +971,7 @@ qcd_colour64_kernel(const double* __restrict__ jbuf, const int64_t* __restrict__
                     acc += zr[q] * X[(2 * (a0 + q)) * NH] + zi[q] * X[(2 * (a0 + q) + 1) * NH];
             }
         }
-        const double me = wave_sum(acc) * Proc::NORM;
+        const double me = wave_sum(acc) * Proc::point_norm(a.pts[kp].gs);
         if (kp == 0) {
             me0 = me;
             if (lane == 0) {

@@ -170,6 +170,20 @@ MGRW_HD v4<T> vvv(const v4<T, A>& J1, const v4<T, B>& J2, const vvv_mom<T>& V, T
     r.z = cmsb(J1.z, j2c, cmad(J2.z, j1b, j12 * d.z));
     return r;
 }
+// The same with the coupling and propagator already in V (V scaled by coup).
+template <typename T, typename A, typename B>
+MGRW_HD v4<T> vvv(const v4<T, A>& J1, const v4<T, B>& J2, const vvv_mom<T>& V) {
+    const r4<T>& d = V.d;
+    cx<T> j12 = dot(J1, J2);
+    cx<T> j1b = dot(J1, V.b);
+    cx<T> j2c = dot(J2, V.c);
+    v4<T> r;
+    r.t = cmsb(J1.t, j2c, cmad(J2.t, j1b, j12 * d.t));
+    r.x = cmsb(J1.x, j2c, cmad(J2.x, j1b, j12 * d.x));
+    r.y = cmsb(J1.y, j2c, cmad(J2.y, j1b, j12 * d.y));
+    r.z = cmsb(J1.z, j2c, cmad(J2.z, j1b, j12 * d.z));
+    return r;
+}
 
 // Four-gluon vertex with propagator: the three colour structures
 //   A = J2 (J1.J3) - J3 (J1.J2)   (colour [1,[2,3]])
@@ -234,9 +248,10 @@ MGRW_HD sp<T> slash_col(const v4<T, A>& J, const sp<T>& v) {
     return b;
 }
 
-// Row spinor times (qslash + m) for a real momentum q, times a real factor.
+// Row spinor times (qslash + m) for a real momentum q (and q, m already
+// scaled by the propagator's denominator where the caller wants it).
 template <typename T>
-MGRW_HD sp<T> row_prop(const sp<T>& b, const lc4<T>& q, T m, T f) {
+MGRW_HD sp<T> row_prop(const sp<T>& b, const lc4<T>& q, T m) {
     const T qp = q.qp, qm = q.qm;
     cx<T> qt = {q.qx, q.qy}, qs = {q.qx, -q.qy};   // q1 + i q2, q1 - i q2
     sp<T> c;
@@ -244,12 +259,11 @@ MGRW_HD sp<T> row_prop(const sp<T>& b, const lc4<T>& q, T m, T f) {
     c.c1 = cmad(b.c2, qs, b.c1 * m) + b.c3 * qm;
     c.c2 = cmsb(b.c1, qt, b.c2 * m + b.c0 * qm);
     c.c3 = cmsb(b.c0, qs, b.c3 * m + b.c1 * qp);
-    return {c.c0 * f, c.c1 * f, c.c2 * f, c.c3 * f};
+    return c;
 }
-
-// (qslash + m) times a column spinor, times a real factor.
+// (qslash + m) times a column spinor, as row_prop.
 template <typename T>
-MGRW_HD sp<T> prop_col(const lc4<T>& q, T m, const sp<T>& v, T f) {
+MGRW_HD sp<T> prop_col(const lc4<T>& q, T m, const sp<T>& v) {
     const T qp = q.qp, qm = q.qm;
     cx<T> qt = {q.qx, q.qy}, qs = {q.qx, -q.qy};
     sp<T> c;
@@ -257,6 +271,18 @@ MGRW_HD sp<T> prop_col(const lc4<T>& q, T m, const sp<T>& v, T f) {
     c.c1 = cmsb(v.c2, qt, v.c1 * m + v.c3 * qp);
     c.c2 = cmad(v.c1, qs, v.c2 * m + v.c0 * qp);
     c.c3 = cmad(v.c0, qt, v.c3 * m) + v.c1 * qm;
+    return c;
+}
+
+// The same times a real factor.
+template <typename T>
+MGRW_HD sp<T> row_prop(const sp<T>& b, const lc4<T>& q, T m, T f) {
+    const sp<T> c = row_prop(b, q, m);
+    return {c.c0 * f, c.c1 * f, c.c2 * f, c.c3 * f};
+}
+template <typename T>
+MGRW_HD sp<T> prop_col(const lc4<T>& q, T m, const sp<T>& v, T f) {
+    const sp<T> c = prop_col(q, m, v);
     return {c.c0 * f, c.c1 * f, c.c2 * f, c.c3 * f};
 }
 
@@ -282,6 +308,15 @@ MGRW_HD sp<T> ffv_col(const v4<T, A>& J, const sp<T>& v, const lc4<T>& q, T m, T
 template <typename T, typename A>
 MGRW_HD sp<T> ffv_row(const sp<T>& a, const v4<T, A>& J, const r4<T>& q, T m, T coup) {
     return ffv_row(a, J, lc4_of(q), m, coup);
+}
+// Unit coupling, with q and m already divided by q^2 - m^2.
+template <typename T, typename A>
+MGRW_HD sp<T> ffv_row(const sp<T>& a, const v4<T, A>& J, const lc4<T>& q, T m) {
+    return row_prop(row_slash(a, J), q, m);
+}
+template <typename T, typename A>
+MGRW_HD sp<T> ffv_col(const v4<T, A>& J, const sp<T>& v, const lc4<T>& q, T m) {
+    return prop_col(q, m, slash_col(J, v));
 }
 template <typename T, typename A>
 MGRW_HD sp<T> ffv_col(const v4<T, A>& J, const sp<T>& v, const r4<T>& q, T m, T coup) {

@@ -356,12 +356,16 @@ class Emitter:
         self.iP_needed.add(t.mask)
         if t.kind == "v3":
             name = self.var("c")
-            self.emit(f"const v4<T> {name} = vvv({kids[0]}, {kids[1]}, {self.vmom(t)}, c.g * k.iP{t.mask});")
+            if self.vertex_kin:   # the record's vertex momenta carry 1/P^2; unit coupling
+                self.emit(f"const v4<T> {name} = vvv({kids[0]}, {kids[1]}, {self.vmom(t)});")
+            else:
+                self.emit(f"const v4<T> {name} = vvv({kids[0]}, {kids[1]}, {self.vmom(t)}, c.g * k.iP{t.mask});")
             self.counts["vvv"] += 1
             self.cache[key] = name
             return name
         q = self.var("c")
-        self.emit(f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, c.g2 * k.iP{t.mask});")
+        g2 = "" if self.vertex_kin else "c.g2 * "
+        self.emit(f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, {g2}k.iP{t.mask});")
         self.counts["vvvv"] += 1
         inner = ",".join(k.key for k in t.kids)
         for p in "ABC":
@@ -383,14 +387,13 @@ class Emitter:
         for t in seq:
             mask |= t.mask
         self.qL_needed.add(mask)
-        if self.vertex_kin:
+        name = self.var("l")
+        if self.vertex_kin:   # momentum and mass carry 1/(q^2 - m^2); unit coupling
             self.QL_needed.add(mask)
-            q = f"k.QL{mask}"
+            self.emit(f"const sp<T> {name} = ffv_row({prev}, {cur}, k.QL{mask}, k.mQL{mask});")
         else:
             self.P_needed.add(mask)
-            q = f"k.pt - k.P{mask}"
-        name = self.var("l")
-        self.emit(f"const sp<T> {name} = ffv_row({prev}, {cur}, {q}, k.mt, c.gk * k.iqL{mask});")
+            self.emit(f"const sp<T> {name} = ffv_row({prev}, {cur}, k.pt - k.P{mask}, k.mt, c.gk * k.iqL{mask});")
         self.counts["ffv_row"] += 1
         glob = self.global_leaf_lr and len(seq) == 1 and seq[0].kind == "leaf"
         (self.global_cache if glob else self.cache)[key] = name
@@ -410,14 +413,13 @@ class Emitter:
         for t in seq:
             mask |= t.mask
         self.qR_needed.add(mask)
+        name = self.var("r")
         if self.vertex_kin:
             self.QR_needed.add(mask)
-            q = f"k.QR{mask}"
+            self.emit(f"const sp<T> {name} = ffv_col({cur}, {nxt}, k.QR{mask}, k.mQR{mask});")
         else:
             self.P_needed.add(mask)
-            q = f"k.P{mask} - k.ptb"
-        name = self.var("r")
-        self.emit(f"const sp<T> {name} = ffv_col({cur}, {nxt}, {q}, k.mt, c.gk * k.iqR{mask});")
+            self.emit(f"const sp<T> {name} = ffv_col({cur}, {nxt}, k.P{mask} - k.ptb, k.mt, c.gk * k.iqR{mask});")
         self.counts["ffv_col"] += 1
         glob = self.global_leaf_lr and len(seq) == 1 and seq[0].kind == "leaf"
         (self.global_cache if glob else self.cache)[key] = name
@@ -484,6 +486,9 @@ class Emitter:
         left, right = self.L(seq[:j]), self.R(seq[j + 1:])
         cur = self.tree(seq[j])
         a = self.var("a")
+        # with unit couplings in the currents the closure carries the top line's
+        # kappa^(number of top-gluon vertices)
+        gk = f"c.gkp[{len(seq)}]" if self.vertex_kin else "c.gk"
         pair = self.lr_key(seq, j)
         if self.lr_uses.get(pair, 0) >= 2:
             # the pair closes several gluon trees in this group: its vector
@@ -494,9 +499,9 @@ class Emitter:
                 self.emit(f"const v4<T> {v} = vector_current({left}, {right});")
                 self.counts["vector_current"] += 1
                 self.vcur[pair] = v
-            self.emit(f"const cx<T> {a} = dot({cur}, {v}) * c.gk;")
+            self.emit(f"const cx<T> {a} = dot({cur}, {v}) * {gk};")
         else:
-            self.emit(f"const cx<T> {a} = ffv_amp({left}, {cur}, {right}, c.gk);")
+            self.emit(f"const cx<T> {a} = ffv_amp({left}, {cur}, {right}, {gk});")
         self.counts["ffv_amp"] += 1
         self.n_amp += 1
         self.accumulate(a, seq)
@@ -522,7 +527,8 @@ class Emitter:
         kids = [self.tree(k) for k in t.kids]
         if t.kind == "v3":
             a = self.var("a")
-            self.emit(f"const cx<T> {a} = dot({jtt}, vvv({kids[0]}, {kids[1]}, {self.vmom(t)}, c.g));")
+            g = "" if self.vertex_kin else ", c.g"
+            self.emit(f"const cx<T> {a} = dot({jtt}, vvv({kids[0]}, {kids[1]}, {self.vmom(t)}{g}));")
             self.counts["vvv_amp"] += 1
             self.n_amp += 1
             self.accumulate(a, seq)
@@ -532,7 +538,8 @@ class Emitter:
         q = self.cache.get(rkey)
         if q is None:
             q = self.var("c")
-            self.emit(f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, c.g2);")
+            g2 = "T(1)" if self.vertex_kin else "c.g2"
+            self.emit(f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, {g2});")
             self.counts["vvvv_amp"] += 1
             self.cache[rkey] = q
         a = self.var("a")
@@ -759,8 +766,10 @@ def emit_process(name, ng, chunks=1, fp64_split=None, vertex_kin=False):
         w(f"    vvv_mom<T> V{m1}_{m2};")
     for m in QL_masks:
         w(f"    lc4<T> QL{m};")
+        w(f"    T mQL{m};")
     for m in QR_masks:
         w(f"    lc4<T> QR{m};")
+        w(f"    T mQR{m};")
     for m in iP_masks:
         w(f"    T iP{m};")
     for m in qL_masks:
@@ -794,9 +803,16 @@ def emit_process(name, ng, chunks=1, fp64_split=None, vertex_kin=False):
         w(f"    double S{m}[4]; for (int m = 0; m < 4; ++m) S{m}[m] = {terms};")
     for m in P_masks:
         w(f"    k.P{m} = {{T(S{m}[0]), T(S{m}[1]), T(S{m}[2]), T(S{m}[3])}};")
+    full = (1 << ng) - 1
     for m1, m2 in V_pairs:
-        w(f"    {{ double d[4], b[4], c[4]; for (int m = 0; m < 4; ++m) {{ d[m] = S{m1}[m] - S{m2}[m]; "
-          f"b[m] = S{m1}[m] + 2.0 * S{m2}[m]; c[m] = S{m2}[m] + 2.0 * S{m1}[m]; }}")
+        # an internal vertex's combinations carry the propagator 1/P^2 of the
+        # line they feed; the root vertex's (P1 + P2 = the t tbar line) do not
+        u = m1 | m2
+        f = "1.0" if u == full else (f"1.0 / (((S{u}[0] * S{u}[0] - S{u}[1] * S{u}[1]) - S{u}[2] * S{u}[2]) - "
+                                     f"S{u}[3] * S{u}[3])")
+        w(f"    {{ const double f = {f}; double d[4], b[4], c[4];")
+        w(f"      for (int m = 0; m < 4; ++m) {{ d[m] = f * (S{m1}[m] - S{m2}[m]); "
+          f"b[m] = f * (S{m1}[m] + 2.0 * S{m2}[m]); c[m] = f * (S{m2}[m] + 2.0 * S{m1}[m]); }}")
         w(f"      k.V{m1}_{m2} = {{{{T(d[0]), T(d[1]), T(d[2]), T(d[3])}}, {{T(b[0]), T(b[1]), T(b[2]), T(b[3])}}, "
           f"{{T(c[0]), T(c[1]), T(c[2]), T(c[3])}}}}; }}")
     for m in iP_masks:
@@ -805,9 +821,12 @@ def emit_process(name, ng, chunks=1, fp64_split=None, vertex_kin=False):
     for side, m_list, qexpr in (("L", qL_masks, "p[2][m] - S{m}[m]"), ("R", qR_masks, "S{m}[m] - p[3][m]")):
         for m in m_list:
             w(f"    {{ double q[4]; for (int m = 0; m < 4; ++m) q[m] = {qexpr.format(m=m)};")
+            w(f"      const double iq = 1.0 / ((((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1]) - q[2] * q[2]) - mt * mt);")
             if m in (QL_masks if side == "L" else QR_masks):
-                w(f"      k.Q{side}{m} = {{T(q[0] + q[3]), T(q[0] - q[3]), T(q[1]), T(q[2])}};")
-            w(f"      k.iq{side}{m} = T(1.0 / ((((q[0] - q[3]) * (q[0] + q[3]) - q[1] * q[1]) - q[2] * q[2]) - mt * mt)); }}")
+                # momentum and mass of the numerator qslash + m, times the denominator
+                w(f"      k.Q{side}{m} = {{T(iq * (q[0] + q[3])), T(iq * (q[0] - q[3])), T(iq * q[1]), T(iq * q[2])}};")
+                w(f"      k.mQ{side}{m} = T(iq * mt);")
+            w(f"      k.iq{side}{m} = T(iq); }}")
     w("  }")
     w("  template <typename T, typename P>")
     w("  static MGRW_HD void external_basis(const P& p, double mt, basis<T>& b) {")
@@ -824,7 +843,34 @@ def emit_process(name, ng, chunks=1, fp64_split=None, vertex_kin=False):
     w(f"    w.ub = ubar_out<T>(b.t, (h >> {next_ - 1 - 2}) & 1 ? 1 : -1);")
     w(f"    w.v = v_out<T>(b.tb, (h >> {next_ - 1 - 3}) & 1 ? 1 : -1);")
     w("  }")
-    w("  template <typename T> struct coup { T g, g2, gk; };")
+    if vertex_kin:
+        # programs reading their vertex momenta from the record take unit strong
+        # couplings (every diagram carries g^NG); kappa enters through gk and,
+        # at the top-vertex closures, through its powers gkp[n]
+        w("  template <typename T> struct coup { T g, g2, gk; T gkp[NG + 1]; };")
+        w("  template <typename T> static MGRW_HD coup<T> couplings(double gs, double gs2, double gk) {")
+        w("    (void)gs2;")
+        w("    const double kap = gk / gs;")
+        w("    coup<T> c;")
+        w("    c.g = T(1);")
+        w("    c.g2 = T(1);")
+        w("    c.gk = T(kap);")
+        w("    double p = 1.0;")
+        w("    for (int i = 0; i <= NG; ++i) { c.gkp[i] = T(p); p *= kap; }")
+        w("    return c;")
+        w("  }")
+        w("  // NORM times g^(2 NG), the strong couplings the programs leave out")
+        w("  static MGRW_HD double point_norm(double gs) {")
+        w("    double f = NORM;")
+        w("    for (int i = 0; i < NG; ++i) f *= gs * gs;")
+        w("    return f;")
+        w("  }")
+    else:
+        w("  template <typename T> struct coup { T g, g2, gk; };")
+        w("  template <typename T> static MGRW_HD coup<T> couplings(double gs, double gs2, double gk) {")
+        w("    return {T(gs), T(gs2), T(gk)};")
+        w("  }")
+        w("  static MGRW_HD double point_norm(double) { return NORM; }")
     w("  // Colour-flow amplitudes J of one helicity (common phase dropped).")
     w("  // k: the event's kin<T> (in registers or in LDS).")
     if body is not None:
