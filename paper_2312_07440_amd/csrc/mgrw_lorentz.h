@@ -185,6 +185,16 @@ MGRW_HD v4<T> vvv(const v4<T, A>& J1, const v4<T, B>& J2, const vvv_mom<T>& V) {
     return r;
 }
 
+// A three-gluon vertex closed on the current K (the t tbar current of a root
+// closure): K . vvv(J1, J2, V) contracted term by term,
+//   (J1.J2)(K.d) + (K.J2)(J1.b) - (K.J1)(J2.c),
+// so that K.J1 and K.J2 are shared between the closures of J1 and J2 with
+// other partners.
+template <typename T, typename A, typename B>
+MGRW_HD cx<T> vvv_close(const v4<T>& K, const v4<T, A>& J1, const v4<T, B>& J2, const vvv_mom<T>& V) {
+    return cmsb(dot(K, J1), dot(J2, V.c), cmad(dot(K, J2), dot(J1, V.b), dot(J1, J2) * dot(K, V.d)));
+}
+
 // Four-gluon vertex with propagator: the three colour structures
 //   A = J2 (J1.J3) - J3 (J1.J2)   (colour [1,[2,3]])
 //   B = J1 (J2.J3) - J3 (J1.J2)   (colour [2,[1,3]])
@@ -218,6 +228,20 @@ MGRW_HD auto vvvv(const v4<T, A>& J1, const v4<T, B>& J2, const v4<T, C>& J3, T 
     o.C.y = cmsb(J2.y, d13, J1.y * d23);
     o.C.z = cmsb(J2.z, d13, J1.z * d23);
     return o;
+}
+
+// The three four-gluon structures closed on the current K (unit coupling):
+// K.A = (K.J2)(J1.J3) - (K.J3)(J1.J2), K.B = (K.J1)(J2.J3) - (K.J3)(J1.J2),
+// K.C = (K.J1)(J2.J3) - (K.J2)(J1.J3).
+template <typename T>
+struct vvvv_closed {
+    cx<T> A, B, C;
+};
+template <typename T, typename A, typename B, typename C>
+MGRW_HD vvvv_closed<T> vvvv_close(const v4<T>& K, const v4<T, A>& J1, const v4<T, B>& J2, const v4<T, C>& J3) {
+    const cx<T> d12 = dot(J1, J2), d13 = dot(J1, J3), d23 = dot(J2, J3);
+    const cx<T> k1 = dot(K, J1), k2 = dot(K, J2), k3 = dot(K, J3);
+    return {cmsb(k3, d12, k2 * d13), cmsb(k3, d12, k1 * d23), cmsb(k2, d13, k1 * d23)};
 }
 
 // Row spinor times a slashed complex vector: (a . Jslash).

@@ -527,8 +527,10 @@ class Emitter:
         kids = [self.tree(k) for k in t.kids]
         if t.kind == "v3":
             a = self.var("a")
-            g = "" if self.vertex_kin else ", c.g"
-            self.emit(f"const cx<T> {a} = dot({jtt}, vvv({kids[0]}, {kids[1]}, {self.vmom(t)}{g}));")
+            if self.vertex_kin:   # unit coupling: contracted term by term
+                self.emit(f"const cx<T> {a} = vvv_close({jtt}, {kids[0]}, {kids[1]}, {self.vmom(t)});")
+            else:
+                self.emit(f"const cx<T> {a} = dot({jtt}, vvv({kids[0]}, {kids[1]}, {self.vmom(t)}, c.g));")
             self.counts["vvv_amp"] += 1
             self.n_amp += 1
             self.accumulate(a, seq)
@@ -538,12 +540,17 @@ class Emitter:
         q = self.cache.get(rkey)
         if q is None:
             q = self.var("c")
-            g2 = "T(1)" if self.vertex_kin else "c.g2"
-            self.emit(f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, {g2});")
+            if self.vertex_kin:
+                self.emit(f"const auto {q} = vvvv_close({jtt}, {kids[0]}, {kids[1]}, {kids[2]});")
+            else:
+                self.emit(f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, c.g2);")
             self.counts["vvvv_amp"] += 1
             self.cache[rkey] = q
         a = self.var("a")
-        self.emit(f"const cx<T> {a} = dot({jtt}, {q}.{t.piece});")
+        if self.vertex_kin:
+            self.emit(f"const cx<T> {a} = {q}.{t.piece};")
+        else:
+            self.emit(f"const cx<T> {a} = dot({jtt}, {q}.{t.piece});")
         self.n_amp += 1
         self.accumulate(a, seq)
 
