@@ -352,6 +352,12 @@ template <typename T, typename A>
 MGRW_HD cx<T> ffv_amp(const sp<T>& a, const v4<T, A>& J, const sp<T>& v, T coup) {
     return row_col(row_slash(a, J), v) * coup;
 }
+// The same closure associated as a . (Jslash . v): it then shares Jslash . v
+// with the column current that continues through this vertex.
+template <typename T, typename A>
+MGRW_HD cx<T> ffv_amp_col(const sp<T>& a, const v4<T, A>& J, const sp<T>& v, T coup) {
+    return row_col(a, slash_col(J, v)) * coup;
+}
 
 // psibar gamma^mu psi' for row spinor a and column spinor b (complex vector).
 template <typename T>

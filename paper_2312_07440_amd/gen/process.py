@@ -317,6 +317,7 @@ class Emitter:
         self.counts = {"vvv": 0, "vvvv": 0, "ffv_row": 0, "ffv_col": 0, "ffv_amp": 0, "vector_current": 0,
                        "vvv_amp": 0, "vvvv_amp": 0, "tt_current": 0}
         self.lr_uses, self.vcur = {}, {}
+        self.col_keys = set()   # column currents the program forms (see close_ttg)
         self.global_cache = {}
         self.cache = {}
         self.global_leaf_lr = global_leaf_lr
@@ -500,6 +501,10 @@ class Emitter:
                 self.counts["vector_current"] += 1
                 self.vcur[pair] = v
             self.emit(f"const cx<T> {a} = dot({cur}, {v}) * {gk};")
+        elif self.vertex_kin and "|".join(t.key for t in seq[j:]) in self.col_keys:
+            # the column current through this vertex exists elsewhere in the
+            # program: share its slashed product
+            self.emit(f"const cx<T> {a} = ffv_amp_col({left}, {cur}, {right}, {gk});")
         else:
             self.emit(f"const cx<T> {a} = ffv_amp({left}, {cur}, {right}, {gk});")
         self.counts["ffv_amp"] += 1
@@ -562,8 +567,25 @@ class Emitter:
             keys.add("leaf" if kind == "leaf" else U)
         return ["leaf"] * ("leaf" in keys) + sorted((k for k in keys if k != "leaf"), key=lambda m: (popcount(m), m))
 
+    def column_keys(self, only=None):
+        """Keys of the column currents a program over `only` forms."""
+        e = Emitter(self.ng, self.global_leaf_lr, self.kpoly, self.flow_range, self.merge_flows, self.vertex_kin)
+        e.col_keys = {None}   # no look-ahead of its own
+        keys = set()
+        plain_R = e.R
+
+        def R(seq):
+            if seq:
+                keys.add("|".join(t.key for t in seq))
+            return plain_R(seq)
+        e.R = R
+        e.program(only)
+        return keys
+
     def program(self, only=None):
         """Emit the program; `only` restricts it to a set of group keys."""
+        if self.vertex_kin and not self.col_keys:
+            self.col_keys = self.column_keys(only) or {None}
         diags = diagrams(self.ng)
         groups = {}
         leaf = []
