@@ -25,9 +25,21 @@ g f^{abc} per three-gluon vertex, -i g^2 per four-gluon vertex) leaves every
 diagram with the common factor i times a sign (-1)^(k-1) (-1)^(#3-gluon nodes)
 for k top vertices; the common factor i is dropped (it cancels in |M|^2).
 
-Couplings are applied inside the chain (g per three-gluon vertex, g^2 per
-four-gluon vertex, g kappa per top-gluon vertex), so evaluating the program at
-a new parameter point is a full re-evaluation of the amplitude.
+Couplings.  Programs that form their vertex momenta themselves apply the
+couplings inside the chain (g per three-gluon vertex, g^2 per four-gluon
+vertex, g kappa per top-gluon vertex).  Programs that read the momentum
+combinations of their vertices from the event record (`vertex_kin`) run at unit
+g -- every diagram carries g^ng, restored on |M|^2 -- and take kappa at each
+top-vertex closure as kappa^b for its b top-gluon vertices; the record's vertex
+and propagator momenta already include the propagator denominators.  Either
+way, evaluating the program at a new parameter point is a full re-evaluation
+of the amplitude.
+
+Closures.  A top-vertex closure ubar_L Jslash v_R uses the vector current of
+its (row, column) pair where that pair closes several trees of a group, and is
+associated as ubar_L (Jslash v_R) where Jslash v_R also starts a column current
+of the program; a root closure contracts the t tbar current with its vertex
+term by term, so that its products with subtree currents are shared.
 """
 from fractions import Fraction
 from functools import lru_cache
