@@ -513,7 +513,7 @@ class Emitter:
                 self.counts["vector_current"] += 1
                 self.vcur[pair] = v
             self.emit(f"const cx<T> {a} = dot({cur}, {v}) * {gk};")
-        elif self.vertex_kin and "|".join(t.key for t in seq[j:]) in self.col_keys:
+        elif "|".join(t.key for t in seq[j:]) in self.col_keys:
             # the column current through this vertex exists elsewhere in the
             # program: share its slashed product
             self.emit(f"const cx<T> {a} = ffv_amp_col({left}, {cur}, {right}, {gk});")
@@ -542,9 +542,10 @@ class Emitter:
         t = seq[0]
         jtt = self.tt_current()
         kids = [self.tree(k) for k in t.kids]
+        unit = self.vertex_kin or self.kpoly   # the vertex carries no coupling
         if t.kind == "v3":
             a = self.var("a")
-            if self.vertex_kin:   # unit coupling: contracted term by term
+            if unit:   # contracted term by term
                 self.emit(f"const cx<T> {a} = vvv_close({jtt}, {kids[0]}, {kids[1]}, {self.vmom(t)});")
             else:
                 self.emit(f"const cx<T> {a} = dot({jtt}, vvv({kids[0]}, {kids[1]}, {self.vmom(t)}, c.g));")
@@ -557,14 +558,14 @@ class Emitter:
         q = self.cache.get(rkey)
         if q is None:
             q = self.var("c")
-            if self.vertex_kin:
+            if unit:
                 self.emit(f"const auto {q} = vvvv_close({jtt}, {kids[0]}, {kids[1]}, {kids[2]});")
             else:
                 self.emit(f"const auto {q} = vvvv({kids[0]}, {kids[1]}, {kids[2]}, c.g2);")
             self.counts["vvvv_amp"] += 1
             self.cache[rkey] = q
         a = self.var("a")
-        if self.vertex_kin:
+        if unit:
             self.emit(f"const cx<T> {a} = {q}.{t.piece};")
         else:
             self.emit(f"const cx<T> {a} = dot({jtt}, {q}.{t.piece});")
@@ -596,7 +597,7 @@ class Emitter:
 
     def program(self, only=None):
         """Emit the program; `only` restricts it to a set of group keys."""
-        if self.vertex_kin and not self.col_keys:
+        if (self.vertex_kin or self.kpoly) and not self.col_keys:
             self.col_keys = self.column_keys(only) or {None}
         diags = diagrams(self.ng)
         groups = {}
