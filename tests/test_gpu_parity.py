@@ -273,6 +273,32 @@ def test_gg_ttggg_parity(torch_dev, n):
     assert e_w.max() <= TOL["mixed"]
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_gg_ttggg_varied_alphas(torch_dev, prec):
+    """g g -> t tbar g g g with alpha_s and kappa varied per point: its
+    programs run at unit strong coupling and restore g_s^10 on |M|^2 per
+    point, in both the single-precision parts and the FP64 pipeline."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 6
+    mom = generate_events("gg_ttggg", n, first_event=555)
+    kap = kappa_points(4)
+    als = [0.100, 0.112, 0.125, 0.135]
+    w = np.random.default_rng(12).normal(size=n)
+    say(f"case gg_ttggg varied alpha_s prec={prec} n={n}")
+    p = mg.Process("gg_ttggg", prec, {"alphas": ALS, "mt": MT})
+    p.set_params([{"alphas": a, "mt": MT, "kappa_ttg": float(k)} for a, k in zip(als, kap)])
+    me0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    out = p.reweight(to_dev(torch, mom), w_in=to_dev(torch, w), me_base_out=me0)
+    torch.cuda.synchronize()
+    me = oracle.qcd_me(5, mom, [(ALS, MT, 1.0)] + [(a, MT, float(k)) for a, k in zip(als, kap)])
+    ref = oracle.reweight(me, w)
+    e_me, e_w = relerr(me0.cpu().numpy(), me[0]), relerr(out.cpu().numpy(), ref)
+    say(f"  |M|^2 rel err max {e_me.max():.3e}; W' rel err max {e_w.max():.3e}")
+    assert e_me.max() <= TOL[prec]
+    assert e_w.max() <= TOL[prec]
+
+
 @pytest.mark.parametrize("n", [1, 70])
 def test_gg_ttggg_fp64_parity(torch_dev, n):
     """g g -> t tbar g g g in FP64 (the program cut by closing-group chunk and
