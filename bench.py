@@ -27,7 +27,7 @@ ALPHA0 = 1 / 132.5
 # HBM traffic of the exact amplitude kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (copy-calibrated; see profiles/), valid only for the sources that
 # kernel is built from: keyed by a fingerprint of those sources.
-MEASURED_TRAFFIC = {("gg_ttgg", "mixed", "e4f376e12a418fc3"): 2204.1}   # bytes per event per launch
+MEASURED_TRAFFIC = {("gg_ttgg", "mixed", "451dee0665104c6f"): 2265.6}   # bytes per event per launch
 WAVE_SECTION = ("// ------------------------------------------------ one event per wave",
                 "// ------------------------------------------------ kappa-polynomial kernels")
 
@@ -50,7 +50,7 @@ def kernel_fingerprint(proc="gg_ttgg"):
 # Executed FP32 flops of the amplitude kernel over the counted (algorithmic)
 # flops of the events it evaluates, from SQ_INSTS_VALU_{FMA,MUL,ADD}_F32
 # (profiles/), for the same kernel sources as MEASURED_TRAFFIC.
-MEASURED_EXEC_RATIO = {("gg_ttgg", "mixed", "e4f376e12a418fc3"): 0.861}
+MEASURED_EXEC_RATIO = {("gg_ttgg", "mixed", "451dee0665104c6f"): 0.861}
 def rescued_events(mom_np, tau):
     """Events the mixed-precision call leaves to its FP64 re-evaluation: a
     gluon pair other than the two beams with |2 p_i.p_j| / s below tau (the
@@ -92,7 +92,13 @@ def flops_per_event(proc, n_points_total, n_hel):
     path = os.path.join(HERE, "paper_2312_07440_amd", "csrc", "gen", "flops.json")
     f = json.load(open(path))[proc]
     n_hel = f.get("evaluated_helicities", n_hel)
-    return n_points_total * n_hel * f["per_helicity_flops"], f
+    per = f["per_helicity_flops"]
+    if n_hel == 64 and "external_flops" in f:
+        # one block of 64 configurations per wave: the external wavefunctions
+        # are assembled once per event, not once per point
+        ext = f["external_flops"]
+        return n_hel * (n_points_total * (per - ext) + ext), f
+    return n_points_total * n_hel * per, f
 
 
 def cpu_baseline(proc, ng, mom_np, kap, gpu_out, sample, points_per_event):

@@ -264,6 +264,14 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
     const typename Proc::template kin<T>& k = ev[el].k;
     const typename Proc::template basis<T>& b = ev[el].b;
     const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
+    // the lane's external wavefunctions live in its own LDS slot: they are
+    // read throughout the program, and in registers they push the program's
+    // working set into scratch.  With one block of 64 configurations they do
+    // not depend on the point and are assembled once per event.
+    __shared__ lds_slot<typename Proc::template ext<T>> wfs[kBlock];
+    typename Proc::template ext<T>& wf = wfs[threadIdx.x].v;
+    constexpr bool one_block = Proc::NHEL == 64;
+    if constexpr (one_block) Proc::template external<T>(b, lane, wf);
     double me0 = 0.0;
 #pragma unroll 1
     for (int kp = 0; kp < a.npts; ++kp) {
@@ -273,12 +281,7 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
 #pragma unroll 1
         for (int hc = 0; hc < Proc::NHEL; hc += 64) {
             __asm__ volatile("" ::: "memory");
-            // the lane's external wavefunctions live in its own LDS slot: they
-            // are read throughout the program, and in registers they push the
-            // program's working set into scratch
-            __shared__ lds_slot<typename Proc::template ext<T>> wfs[kBlock];
-            typename Proc::template ext<T>& wf = wfs[threadIdx.x].v;
-            Proc::template external<T>(b, hc + lane, wf);
+            if constexpr (!one_block) Proc::template external<T>(b, hc + lane, wf);
             cx<T> J[Proc::K];
             Proc::amplitude(wf, kin_near_use(k), c, J);
             acc += double(Proc::colour_sum(J));
@@ -460,6 +463,10 @@ qcd_rescue_kernel(const double* __restrict__ mom, const int64_t* __restrict__ li
             for (int q = 0; q < kpoly_pairs<Proc>(); ++q) B[q] = wave_sum(B[q]);
             if (lane == 0) kpoly_outputs<Proc>(B, a, n, e, w, out, me0_out);
         } else {
+            typename Proc::template ext<double>& wf = wfs[threadIdx.x].v;   // own slot
+            // one block of 64 configurations: assembled once for all points
+            constexpr bool one_block = Proc::NHEL == 64;
+            if constexpr (one_block) Proc::template external<double>(d.b, lane, wf);
             double me0 = 0.0;
 #pragma unroll 1
             for (int kp = 0; kp < a.npts; ++kp) {
@@ -469,8 +476,7 @@ qcd_rescue_kernel(const double* __restrict__ mom, const int64_t* __restrict__ li
 #pragma unroll 1
                 for (int hc = 0; hc < Proc::NHEL; hc += 64) {
                     if (hc + lane < Proc::NHEL) {
-                        typename Proc::template ext<double>& wf = wfs[threadIdx.x].v;   // own slot
-                        Proc::template external<double>(d.b, hc + lane, wf);
+                        if constexpr (!one_block) Proc::template external<double>(d.b, hc + lane, wf);
                         cx<double> J[Proc::K];
                         Proc::amplitude(wf, d.k, c, J);
                         acc += Proc::colour_sum(J);
