@@ -149,33 +149,39 @@ struct ee_photons {
 #if defined(__HIP_DEVICE_COMPILE__)
 #pragma unroll
 #endif
+        // Each product is added to its running sum on its own (cmad/cmsb:
+        // fused multiply-adds); the first term of a sum starts it.
         for (int mask = 1; mask < NSUB; ++mask) {
-            cx<T> ua = {T(0), T(0)}, ub = {T(0), T(0)};
+            cx<T> ua, ub;
+            bool first = true;   // a constant in every unrolled step
 #if defined(__HIP_DEVICE_COMPILE__)
 #pragma unroll
 #endif
             for (int i = 0; i < NA; ++i) {
                 if (!(mask >> i & 1)) continue;
                 const wspin<T>& x = R[mask & ~(1 << i)];
-                ua = ua + va[i] * x.a + vb[i] * x.b;
-                ub = ub + vc[i] * x.a - va[i] * x.b;
+                ua = cmad(vb[i], x.b, first ? va[i] * x.a : cmad(va[i], x.a, ua));
+                ub = cmsb(va[i], x.b, first ? vc[i] * x.a : cmad(vc[i], x.a, ub));
+                first = false;
             }
             // P(q) = [[A + sZ, s(X - iY)], [s(X + iY), A - sZ]] with (A, X, Y, Z) = q / q^2
             const T A = ev.P[mask][0], X = s * ev.P[mask][1], Y = s * ev.P[mask][2], Z = s * ev.P[mask][3];
             const cx<T> xmy = {X, -Y}, xpy = {X, Y};
-            R[mask] = {(A + Z) * ua + xmy * ub, xpy * ua + (A - Z) * ub};
+            R[mask] = {cmad(xmy, ub, (A + Z) * ua), cmad(xpy, ua, (A - Z) * ub)};
         }
-        cx<T> ta = {T(0), T(0)}, tb = {T(0), T(0)};
+        cx<T> ta = va[0] * R[NSUB & ~1].a, tb = vc[0] * R[NSUB & ~1].a;
+        ta = cmad(vb[0], R[NSUB & ~1].b, ta);
+        tb = cmsb(va[0], R[NSUB & ~1].b, tb);
 #if defined(__HIP_DEVICE_COMPILE__)
 #pragma unroll
 #endif
-        for (int i = 0; i < NA; ++i) {
+        for (int i = 1; i < NA; ++i) {
             const wspin<T>& x = R[NSUB & ~(1 << i)];
-            ta = ta + va[i] * x.a + vb[i] * x.b;
-            tb = tb + vc[i] * x.a - va[i] * x.b;
+            ta = cmad(vb[i], x.b, cmad(va[i], x.a, ta));
+            tb = cmsb(va[i], x.b, cmad(vc[i], x.a, tb));
         }
         // -chi_lam(p0)^dagger (ta, tb)
-        return -(conj(ev.chi0[li][0]) * ta + conj(ev.chi0[li][1]) * tb);
+        return -cmad(conj(ev.chi0[li][1]), tb, conj(ev.chi0[li][0]) * ta);
     }
 };
 
