@@ -27,7 +27,7 @@ ALPHA0 = 1 / 132.5
 # HBM traffic of the exact amplitude kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (copy-calibrated; see profiles/), valid only for the sources that
 # kernel is built from: keyed by a fingerprint of those sources.
-MEASURED_TRAFFIC = {("gg_ttgg", "mixed", "451dee0665104c6f"): 2265.6}   # bytes per event per launch
+MEASURED_TRAFFIC = {("gg_ttgg", "mixed", "0ed74d1fbbe9ee7b"): 2398.2}   # bytes per event per launch
 WAVE_SECTION = ("// ------------------------------------------------ one event per wave",
                 "// ------------------------------------------------ kappa-polynomial kernels")
 
@@ -50,7 +50,7 @@ def kernel_fingerprint(proc="gg_ttgg"):
 # Executed FP32 flops of the amplitude kernel over the counted (algorithmic)
 # flops of the events it evaluates, from SQ_INSTS_VALU_{FMA,MUL,ADD}_F32
 # (profiles/), for the same kernel sources as MEASURED_TRAFFIC.
-MEASURED_EXEC_RATIO = {("gg_ttgg", "mixed", "451dee0665104c6f"): 0.861}
+MEASURED_EXEC_RATIO = {("gg_ttgg", "mixed", "0ed74d1fbbe9ee7b"): 0.861}
 def rescued_events(mom_np, tau):
     """Events the mixed-precision call leaves to its FP64 re-evaluation: a
     gluon pair other than the two beams with |2 p_i.p_j| / s below tau (the

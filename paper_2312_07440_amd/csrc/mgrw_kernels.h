@@ -231,17 +231,21 @@ qcd_setup_kernel(const double* __restrict__ mom, int64_t n, int64_t e0, int64_t 
     ev[el].skip = skip;
 }
 
-// An event's kinematics record as the generated programs should read it:
-// each value loaded where the program uses it, into vector registers.  The
-// record is wave-uniform, and read through its plain address the compiler
-// loads it into scalar registers ahead of the program and, having too few,
-// spills them to vector lanes (a vector instruction per spill and reload);
-// an opaque copy of the address makes it load each value near its use.  The
+// An event's kinematics record, staged in LDS, as the generated programs
+// should read it: each value loaded where the program uses it.  The record is
+// wave-uniform; read through its plain address the compiler loads all of it
+// ahead of the program and spills (from global memory: into scalar registers,
+// then to vector lanes; from LDS: into vector registers, then to scratch).
+// An opaque copy of the address keeps each read next to its use, and the
+// assumption keeps the reads LDS reads (ds_read) rather than flat loads.  The
 // address must be wave-uniform (it is held in scalar registers).
 template <class K>
-__device__ __forceinline__ const K& kin_near_use(const K& k) {
+__device__ __forceinline__ const K& lds_near_use(const K& k) {
     const K* p = &k;
     __asm__ volatile("" : "+s"(p));
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_assume(__builtin_amdgcn_is_shared(reinterpret_cast<const void*>(p)));
+#endif
     return *p;
 }
 
@@ -261,7 +265,22 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
     if (el >= nb || ev[el].skip) return;   // whole wave; no barriers below
     const int64_t e = e0 + el;
     const int lane = threadIdx.x & 63;
-    const typename Proc::template kin<T>& k = ev[el].k;
+    // the event's kinematics record, staged once per event in LDS (one record
+    // per wave): the program reads it with broadcast LDS loads
+    using KIN = typename Proc::template kin<T>;
+    struct alignas(16) kin_slot { KIN v; };
+    static_assert(sizeof(KIN) % 4 == 0, "record copied in 32-bit words");
+    __shared__ kin_slot kl[kBlock / 64];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&ev[el].k);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&kl[wv].v);
+        for (int i = lane; i < int(sizeof(KIN) / 4); i += 64) dst[i] = src[i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    const KIN& k = kl[wv].v;
     const typename Proc::template basis<T>& b = ev[el].b;
     const double w = (a.mode == 0 && w_in) ? w_in[e] : 1.0;
     // the lane's external wavefunctions live in its own LDS slot: they are
@@ -283,7 +302,7 @@ qcd_wave_kernel(const event_data<Proc, T>* __restrict__ ev, int64_t e0, int64_t 
             __asm__ volatile("" ::: "memory");
             if constexpr (!one_block) Proc::template external<T>(b, hc + lane, wf);
             cx<T> J[Proc::K];
-            Proc::amplitude(wf, kin_near_use(k), c, J);
+            Proc::amplitude(wf, lds_near_use(k), c, J);
             acc += double(Proc::colour_sum(J));
         }
         const double me = wave_sum(acc) * Proc::point_norm(pt.gs);
