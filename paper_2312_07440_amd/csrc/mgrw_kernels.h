@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "../../include/mgrw.h"
@@ -68,6 +69,32 @@ struct qed_launch {
 // Device-side timestamps around the amplitude kernel(s) of a launch.
 inline void mark(hipEvent_t ev, hipStream_t s) {
     if (ev) (void)hipEventRecord(ev, s);
+}
+
+// Library-owned streams of the current device (default priority, created on
+// first use, kept until the process ends), on which independent kernels of
+// one call run beside the caller's stream.
+constexpr int kAuxStreams = 3;
+constexpr int kMaxDevices = 64;
+inline hipError_t aux_streams(hipStream_t* out) {
+    static std::mutex mu;
+    static hipStream_t pool[kMaxDevices][kAuxStreams] = {};
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < kAuxStreams; ++i) {
+        if (!pool[dev][i]) {
+            err = hipStreamCreateWithFlags(&pool[dev][i], hipStreamNonBlocking);
+            if (err != hipSuccess) {
+                pool[dev][i] = nullptr;
+                return err;
+            }
+        }
+        out[i] = pool[dev][i];
+    }
+    return hipSuccess;
 }
 
 template <int NEXT>
@@ -1065,10 +1092,44 @@ hipError_t launch_split64(const split_launchers<Proc>& L, const double* mom, int
                        mom, n, a.mt, list, count, slots, ev);
     err = hipGetLastError();
     if (timed) mark(a.t0, s);
+    // Re-evaluating listed events, a batch holds few of them and one (chunk,
+    // range) kernel leaves most SIMDs idle: the ranges of a chunk, which
+    // write disjoint parts of jbuf, then run side by side, range 0 on the
+    // caller's stream and the others on library streams, joined per chunk.
+    constexpr int NFR = Proc::NFR;
+    const bool side = list != nullptr && NFR - 1 <= kAuxStreams;
+    hipStream_t aux[kAuxStreams] = {};
+    hipEvent_t fork = nullptr, join[kAuxStreams] = {};
+    if (err == hipSuccess && side) {
+        err = aux_streams(aux);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        for (int r = 1; r < NFR && err == hipSuccess; ++r) err = hipEventCreateWithFlags(&join[r - 1], hipEventDisableTiming);
+    }
     for (int64_t e0 = 0; e0 < slots && err == hipSuccess; e0 += B) {
         const int64_t nb = slots - e0 < B ? slots - e0 : B;
-        for (int q = 0; q < Proc::NCHUNK64 * Proc::NFR && err == hipSuccess; ++q)
-            err = L.fr[q](ev, count, e0, nb, jbuf, a, s);
+        for (int c = 0; c < Proc::NCHUNK64 && err == hipSuccess; ++c) {
+            if (!side) {
+                for (int r = 0; r < NFR && err == hipSuccess; ++r) err = L.fr[c * NFR + r](ev, count, e0, nb, jbuf, a, s);
+                continue;
+            }
+            err = hipEventRecord(fork, s);
+            for (int r = 1; r < NFR && err == hipSuccess; ++r) err = hipStreamWaitEvent(aux[r - 1], fork, 0);
+            if (err == hipSuccess) err = L.fr[c * NFR](ev, count, e0, nb, jbuf, a, s);
+            bool used[kAuxStreams] = {};
+            for (int r = 1; r < NFR && err == hipSuccess; ++r) {
+                used[r - 1] = true;   // a failed launch may still have queued work
+                err = L.fr[c * NFR + r](ev, count, e0, nb, jbuf, a, aux[r - 1]);
+            }
+            // join every library stream that received work, also after an
+            // error, before the buffers are released on the caller's stream
+            for (int r = 1; r < NFR; ++r) {
+                if (!used[r - 1]) continue;
+                hipError_t j = hipEventRecord(join[r - 1], aux[r - 1]);
+                if (j == hipSuccess) j = hipStreamWaitEvent(s, join[r - 1], 0);
+                if (j != hipSuccess) (void)hipStreamSynchronize(aux[r - 1]);
+                if (err == hipSuccess) err = j;
+            }
+        }
         if (err == hipSuccess) {
             hipLaunchKernelGGL((qcd_colour64_kernel<Proc>), dim3(unsigned((nb + kBlock / 64 - 1) / (kBlock / 64))),
                                dim3(kBlock), 0, s, jbuf, list, count, e0, nb, w_in, n, a, out, me0);
@@ -1076,6 +1137,10 @@ hipError_t launch_split64(const split_launchers<Proc>& L, const double* mom, int
         }
     }
     if (timed) mark(a.t1, s);
+    // the events are released once their pending work has completed
+    if (fork) (void)hipEventDestroy(fork);
+    for (int r = 0; r < kAuxStreams; ++r)
+        if (join[r]) (void)hipEventDestroy(join[r]);
     hipError_t f1 = hipFreeAsync(jbuf, s), f2 = hipFreeAsync(ev, s);
     return err != hipSuccess ? err : (f1 != hipSuccess ? f1 : f2);
 }
