@@ -1092,12 +1092,14 @@ hipError_t launch_split64(const split_launchers<Proc>& L, const double* mom, int
                        mom, n, a.mt, list, count, slots, ev);
     err = hipGetLastError();
     if (timed) mark(a.t0, s);
-    // Re-evaluating listed events, a batch holds few of them and one (chunk,
-    // range) kernel leaves most SIMDs idle: the ranges of a chunk, which
-    // write disjoint parts of jbuf, then run side by side, range 0 on the
-    // caller's stream and the others on library streams, joined per chunk.
+    // One (chunk, range) kernel at one wave per SIMD leaves SIMDs idle: with
+    // few events per batch (re-evaluating listed events) most of them, and in
+    // the last round of waves of a full batch nearly all.  The ranges of a
+    // chunk write disjoint parts of jbuf, so they run side by side, range 0
+    // on the caller's stream and the others on library streams, joined per
+    // chunk.
     constexpr int NFR = Proc::NFR;
-    const bool side = list != nullptr && NFR - 1 <= kAuxStreams;
+    const bool side = NFR - 1 <= kAuxStreams;
     hipStream_t aux[kAuxStreams] = {};
     hipEvent_t fork = nullptr, join[kAuxStreams] = {};
     if (err == hipSuccess && side) {
