@@ -170,6 +170,39 @@ def test_gg_ttggg_rescue_replaces_only_flagged_events(torch_dev):
     assert np.abs(outs["on"][1][fl] / outs["fp64"][1][fl] - 1).max() <= 1e-12
 
 
+def test_gg_ttggg_split_pipeline_repeatable_on_a_side_stream(torch_dev):
+    """The double-precision pipeline of g g -> t tbar g g g runs the flow
+    ranges of each chunk on the caller's stream and on library streams,
+    joined per chunk: repeated calls on a stream of the caller's own, mixed
+    precision (its listed events go through the pipeline) and FP64, give
+    bit-identical weights, also with other work queued on the stream."""
+    import paper_2312_07440_amd as mg
+    torch = torch_dev
+    n = 2500
+    mom_np = generate_events("gg_ttggg", n, first_event=777)
+    fl = flagged(mom_np, TAU)
+    say(f"case split pipeline repeatable gg_ttggg n={n}: {fl.sum()} flagged")
+    assert fl.sum() > 0
+    mom = torch.from_numpy(mom_np).to("cuda:0")
+    kap = kappa_points(4)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for prec in ("mixed", "fp64"):
+        say(f"  {prec}")
+        p = mg.Process("gg_ttggg", prec)
+        p.set_params([{"kappa_ttg": float(k)} for k in kap])
+        if prec == "mixed":
+            p.set_rescue_threshold(TAU)
+        with torch.cuda.stream(side):
+            a = p.reweight(mom, stream=side)
+            filler = torch.ones(1 << 20, device="cuda:0").cumsum(0)   # other work on the stream
+            b = p.reweight(mom, stream=side)
+        side.synchronize()
+        assert torch.isfinite(a).all()
+        assert torch.equal(a, b)
+        assert float(filler[-1]) == float(1 << 20)
+
+
 def test_rescue_applies_to_eval_me(torch_dev):
     import paper_2312_07440_amd as mg
     torch = torch_dev
