@@ -26,6 +26,10 @@
  *  - `stream` is a hipStream_t (NULL: the default stream).  Evaluation calls
  *    are asynchronous and stream-ordered; argument errors are reported before
  *    anything is launched, device faults surface at a later synchronisation.
+ *    The double-precision pipeline of g g -> t tbar g g g also runs kernels on
+ *    three library-owned streams of the device (default priority, created on
+ *    first use, kept until the process ends), forked from and joined back
+ *    into `stream` with events, so the call stays ordered on `stream`.
  *  - Return values are mgrw_status codes; on a non-OK status the calling
  *    thread's mgrw_last_error() describes it.  No exception crosses the ABI.
  *  - A process handle is not thread-safe; distinct handles are independent.
